@@ -1,0 +1,161 @@
+/*
+ * libjpet — list-mode MLEM reconstruction for the two-strip J-PET detector on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is that of P. Bialas et al., "GPU accelerated image reconstruction in a
+ * two-strip J-PET tomograph" (arXiv:1502.07478):
+ *   - events are the triples (z_u, z_d, dl) of the Setup section (Eq. 1),
+ *   - the per-pixel sensitivity is Eq. 4,
+ *   - the event kernel P(e|i) is Eq. 7 with the vectors of Eq. 8-11 and the diagonal
+ *     C^-1 of Eq. 12 (gamma = 0),
+ *   - it is evaluated over the pixel centres inside the 3-sigma ellipse of each event
+ *     (Sec. 3, last paragraph; bounding box of App. B),
+ *   - one iteration is the two-pass scheme of the implementation listing (Sec. 4):
+ *     D_j = sum_i P_ji rho_i, then rho_l P_jl / D_j is accumulated into the new image,
+ *     which is divided by the sensitivity (Eq. 3; Eq. 5 when no sensitivity is given).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units are millimetres.  The detector strips lie at y = +R (upper) and y = -R (lower) and
+ * span z in [-L/2, L/2].  Images are float32, row-major [n_y][n_z]; pixel (i, k) is the
+ * square of side `pixel` centred at
+ *     y_i = (i + 1/2 - n_y/2) * pixel,   z_k = (k + 1/2 - n_z/2) * pixel.
+ * Events are float32 [n][3] rows (z_u, z_d, dl) (array of structures, 12 bytes each).
+ *
+ * Memory: every array argument is DEVICE memory on the current HIP device, owned by the
+ * caller, unless the argument says "host".  The library allocates no device memory in
+ * any entry point below; scratch space is the caller's workspace.  It keeps no pointer
+ * after a call returns.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the legacy default stream).  Work is enqueued
+ * asynchronously; outputs are valid once the stream has been synchronised, except that an
+ * entry point given a non-NULL host `stats` pointer synchronises the stream before it
+ * returns.  Calls that share a workspace must be ordered (same stream, or synchronised);
+ * calls with distinct workspaces are independent and the library is reentrant.
+ *
+ * Errors: every entry point returns 0 (JPET_OK) or a negative code.  Arguments are fully
+ * validated before anything is enqueued or written; on a validation error nothing is
+ * written.  There are no C++ exceptions across this interface.
+ */
+#ifndef JPET_H
+#define JPET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JPET_ABI_VERSION 1
+
+enum jpet_status {
+  JPET_OK = 0,
+  JPET_EINVAL = -1,     /* a required pointer is NULL, a count is negative, flags are unknown */
+  JPET_EDOMAIN = -2,    /* geometry out of domain (see jpet_geometry); log-likelihood is -inf */
+  JPET_EWORKSPACE = -3, /* workspace NULL or smaller than the size query returned */
+  JPET_EHIP = -4,       /* a HIP runtime call failed; jpet_last_hip_error() has its code */
+  JPET_ENOTSUP = -5     /* valid request that this build does not implement (e.g. gamma != 0) */
+};
+
+/* Detector, resolution and pixel grid.  All members are read by value; the struct is
+ * host memory.  Domain (else JPET_EDOMAIN): R, L, sigma_z, sigma_dl, pixel finite and > 0;
+ * 0 < n_y, n_z <= 32768; n_y * pixel / 2 < R (every pixel centre lies between the strips);
+ * kernel_variant in {0, 1}.  gamma must be 0 (else JPET_ENOTSUP). */
+typedef struct jpet_geometry {
+  double R;              /* strip half-separation: strips at y = +R and y = -R (Setup, Eq. 1) */
+  double L;              /* strip length; strips span z in [-L/2, L/2] (Eq. 4) */
+  double sigma_z;        /* resolution of z_u and z_d (Eq. 12) */
+  double sigma_dl;       /* resolution of dl (Eq. 12) */
+  double gamma;          /* off-diagonal element of C^-1 (Eq. 12); must be 0 */
+  double pixel;          /* pixel pitch, the same along y and z */
+  int32_t n_y;           /* number of pixel rows (y) */
+  int32_t n_z;           /* number of pixel columns (z) */
+  int32_t kernel_variant;/* third component of a (Eq. 9): 0 as printed, 1 twice that (the
+                            exact derivative of dl with respect to the emission angle) */
+  int32_t reserved;      /* must be 0 */
+} jpet_geometry;
+
+/* Per-call counters (host memory).  An event is valid when its three numbers are finite,
+ * |z_u| <= L/2, |z_d| <= L/2 and at least one pixel centre of the grid lies inside its
+ * 3-sigma ellipse; other events are dropped (counted, not an error).  A valid event whose
+ * denominator D is 0 (the current image vanishes on its ellipse) is skipped by the update
+ * and counted in n_zero_denominator (value for the last iteration). */
+typedef struct jpet_stats {
+  int64_t n_events;
+  int64_t n_valid;
+  int64_t n_dropped;
+  int64_t n_zero_denominator;
+  int64_t n_pairs;             /* (valid event, in-ellipse pixel) pairs per iteration */
+  int64_t n_kappa_nonpositive; /* in-ellipse pairs whose Eq. 7 denominator term is <= 0 (P := 0) */
+} jpet_stats;
+
+/* Flags for jpet_mlem_iterate and jpet_loglik_grad. */
+#define JPET_WS_PREPARED 1u /* the workspace already holds jpet_mlem_prepare's output for
+                               exactly this geometry and event array; skip that step */
+
+/* Text for a status code (static storage, never NULL). */
+const char* jpet_strerror(int status);
+
+/* The hipError_t of the last failed HIP call made by this thread inside the library
+ * (0 if none). */
+int jpet_last_hip_error(void);
+
+/* ABI version compiled into the library (JPET_ABI_VERSION). */
+int jpet_abi_version(void);
+
+/* Sensitivity image, Eq. 4: for each pixel centre (y, z) the fraction of in-plane emission
+ * directions, uniform in angle, whose line meets both strips:
+ *   s = (atan(min((L/2 - z)/(R - y), (L/2 + z)/(R + y)))
+ *        - atan(max(-(L/2 + z)/(R - y), (z - L/2)/(R + y)))) / pi, clamped at 0.
+ * Evaluated in double precision and rounded to float.
+ *   s_out: device float [n_y * n_z], written entirely. */
+int jpet_sensitivity(const jpet_geometry* g, float* s_out, void* stream);
+
+/* Bytes of workspace that jpet_mlem_prepare / jpet_mlem_iterate / jpet_loglik_grad need for
+ * n_events events on this geometry (host output *bytes).  The workspace is any device
+ * allocation of at least that size, aligned to 256 bytes. */
+int jpet_mlem_workspace_size(const jpet_geometry* g, int64_t n_events, size_t* bytes);
+
+/* Iteration-invariant per-event work, done once per event list: direct reconstruction (Eq. 2),
+ * the 3-sigma ellipse's pixel rows (App. B) and validity, and the spatial ordering of events
+ * used by the event pass.  Writes only the workspace.
+ *   events: device float [n][3]; n >= 0. */
+int jpet_mlem_prepare(const jpet_geometry* g, const float* events, int64_t n, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* n_iter list-mode MLEM iterations (Sec. 4 listing, Eq. 3) in place on rho.
+ *   events: device float [n][3]
+ *   s:      device float [n_y*n_z] sensitivity (e.g. from jpet_sensitivity), or NULL for the
+ *           Eq. 5 form in which no sensitivity is applied (s = 1 everywhere)
+ *   rho:    device float [n_y*n_z], the current image on entry, the image after n_iter
+ *           iterations on return.  rho must be finite and >= 0.  Pixels with s = 0 are set to 0.
+ *   n_iter >= 0; flags: 0 or JPET_WS_PREPARED; stats: host, nullable (synchronises if given).
+ * One iteration: for every valid event j, D_j = sum_{i in ellipse} P_ji rho_i; for D_j > 0 the
+ * values rho_l P_jl / D_j are summed into the new image; then rho_l = sum / s_l (s_l > 0) or 0. */
+int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, const float* s, float* rho,
+                      int32_t n_iter, void* ws, size_t ws_bytes, uint32_t flags, jpet_stats* stats,
+                      void* stream);
+
+/* Poisson list-mode log-likelihood of the image and its gradient (the objective whose EM step
+ * is Eq. 3):
+ *   l = sum_{valid j} log(D_j / pi) - sum_l s_l rho_l,     D_j = sum_{i in ellipse_j} P_ji rho_i
+ *   dl/drho_l = sum_j P_jl / D_j - s_l
+ *   dl/dsigma_z, dl/dsigma_dl: derivatives of l through P (Eq. 7) with the ellipse mask held
+ *   fixed.  The mask is the 3-sigma ellipse at (sigma_mask[0], sigma_mask[1]) (host double[2],
+ *   nullable = the geometry's sigmas); the kernel uses the geometry's sigmas.
+ *   out3:     device double[3] = { l, dl/dsigma_z, dl/dsigma_dl }, sums in double precision
+ *   grad_rho: device float [n_y*n_z] or NULL
+ *   D_out:    device float [n] per-event D_j (0 for dropped events) or NULL
+ *   s:        as for jpet_mlem_iterate (NULL = 1)
+ * Returns JPET_EDOMAIN (after writing l = -inf) when a valid event has D_j = 0; this case
+ * synchronises the stream to read the count. */
+int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const float* events, int64_t n,
+                     const float* s, const float* rho, double* out3, float* grad_rho, float* D_out, void* ws,
+                     size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JPET_H */

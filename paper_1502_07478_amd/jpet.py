@@ -1,0 +1,200 @@
+"""Python binding of libjpet (ctypes).  Argument marshalling only: every step of the
+reconstruction runs in the library's HIP kernels; torch provides device memory and streams.
+
+Images are float32 CUDA tensors of shape [n_y, n_z] (row-major), events float32 [n, 3]
+(z_u, z_d, dl) in millimetres.  See include/jpet.h for the contract of each call.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjpet.so")
+
+JPET_OK, JPET_EINVAL, JPET_EDOMAIN, JPET_EWORKSPACE, JPET_EHIP, JPET_ENOTSUP = 0, -1, -2, -3, -4, -5
+JPET_WS_PREPARED = 1
+
+
+class JpetError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib().jpet_strerror(code).decode()
+        if code == JPET_EHIP:
+            msg += f" (hipError {_lib().jpet_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{code}]")
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [
+        ("R", ctypes.c_double), ("L", ctypes.c_double), ("sigma_z", ctypes.c_double),
+        ("sigma_dl", ctypes.c_double), ("gamma", ctypes.c_double), ("pixel", ctypes.c_double),
+        ("n_y", ctypes.c_int32), ("n_z", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    @property
+    def shape(self):
+        return (int(self.n_y), int(self.n_z))
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_events", ctypes.c_int64), ("n_valid", ctypes.c_int64), ("n_dropped", ctypes.c_int64),
+        ("n_zero_denominator", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+        ("n_kappa_nonpositive", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+_L = None
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libjpet.so is not built ({LIB_PATH}); run paper_1502_07478_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, gp, sp = ctypes.c_void_p, ctypes.POINTER(Geometry), ctypes.POINTER(Stats)
+        i64, sz, u32, i32 = ctypes.c_int64, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_int32
+        L.jpet_strerror.argtypes = [ctypes.c_int]
+        L.jpet_strerror.restype = ctypes.c_char_p
+        L.jpet_last_hip_error.argtypes = []
+        L.jpet_abi_version.argtypes = []
+        L.jpet_sensitivity.argtypes = [gp, vp, vp]
+        L.jpet_mlem_workspace_size.argtypes = [gp, i64, ctypes.POINTER(sz)]
+        L.jpet_mlem_prepare.argtypes = [gp, vp, i64, vp, sz, vp]
+        L.jpet_mlem_iterate.argtypes = [gp, vp, i64, vp, vp, i32, vp, sz, u32, sp, vp]
+        L.jpet_loglik_grad.argtypes = [gp, ctypes.POINTER(ctypes.c_double), vp, i64, vp, vp, vp, vp, vp, vp, sz,
+                                       u32, sp, vp]
+        _L = L
+    return _L
+
+
+def lib():
+    """The loaded libjpet (raises if it is not built)."""
+    return _lib()
+
+
+def geometry(R, L, sigma_z, sigma_dl, pixel, n_y, n_z, kernel_variant=0, gamma=0.0) -> Geometry:
+    return Geometry(float(R), float(L), float(sigma_z), float(sigma_dl), float(gamma), float(pixel), int(n_y),
+                    int(n_z), int(kernel_variant), 0)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(rc: int, where: str):
+    if rc != JPET_OK:
+        raise JpetError(rc, where)
+
+
+def _need(t, name, dtype, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def sensitivity(g: Geometry, device=None, stream=None) -> torch.Tensor:
+    out = torch.empty(g.shape, dtype=torch.float32, device=device or "cuda")
+    _check(_lib().jpet_sensitivity(ctypes.byref(g), _ptr(out), _stream(stream)), "jpet_sensitivity")
+    return out
+
+
+def workspace_size(g: Geometry, n_events: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_lib().jpet_mlem_workspace_size(ctypes.byref(g), int(n_events), ctypes.byref(b)), "jpet_mlem_workspace_size")
+    return int(b.value)
+
+
+def workspace(g: Geometry, n_events: int, device=None) -> torch.Tensor:
+    return torch.empty(workspace_size(g, n_events), dtype=torch.uint8, device=device or "cuda")
+
+
+def _events(events):
+    _need(events, "events", torch.float32)
+    if events.dim() != 2 or events.shape[1] != 3:
+        raise ValueError("events must be [n, 3]")
+    return events
+
+
+def prepare(g: Geometry, events: torch.Tensor, ws: torch.Tensor, stream=None):
+    """Iteration-invariant per-event work (direct reconstruction, ellipse rows) into ws."""
+    _events(events)
+    _check(_lib().jpet_mlem_prepare(ctypes.byref(g), _ptr(events), events.shape[0], _ptr(ws), ws.numel(),
+                                    _stream(stream)), "jpet_mlem_prepare")
+
+
+def mlem_iterate(g: Geometry, events: torch.Tensor, rho: torch.Tensor, n_iter: int, s: torch.Tensor | None = None,
+                 ws: torch.Tensor | None = None, prepared: bool = False, want_stats: bool = False, stream=None):
+    """n_iter MLEM iterations in place on rho; returns the stats dict when want_stats."""
+    _events(events)
+    _need(rho, "rho", torch.float32, g.shape)
+    if s is not None:
+        _need(s, "s", torch.float32, g.shape)
+    if ws is None:
+        ws = workspace(g, events.shape[0], rho.device)
+        prepared = False
+    st = Stats() if want_stats else None
+    rc = _lib().jpet_mlem_iterate(ctypes.byref(g), _ptr(events), events.shape[0], _ptr(s), _ptr(rho), int(n_iter),
+                                  _ptr(ws), ws.numel(), JPET_WS_PREPARED if prepared else 0,
+                                  ctypes.byref(st) if st is not None else None, _stream(stream))
+    _check(rc, "jpet_mlem_iterate")
+    return st.as_dict() if st is not None else None
+
+
+def mlem(events: torch.Tensor, g: Geometry, n_iter: int, sens: torch.Tensor | None = None,
+         rho0: torch.Tensor | None = None):
+    """Reconstruct from rho0 (default: 1 where sens > 0, or 1 everywhere without sens)."""
+    if rho0 is None:
+        rho = (sens > 0).to(torch.float32) if sens is not None else torch.ones(g.shape, device=events.device)
+    else:
+        rho = rho0.clone()
+    mlem_iterate(g, events, rho, n_iter, s=sens)
+    return rho
+
+
+@dataclass
+class LogLik:
+    value: torch.Tensor        # device double[3]: l, dl/dsigma_z, dl/dsigma_dl
+    grad_rho: torch.Tensor | None
+    D: torch.Tensor | None
+    stats: dict | None
+
+
+def loglik_grad(g: Geometry, events: torch.Tensor, rho: torch.Tensor, s: torch.Tensor | None = None,
+                sigma_mask=None, want_grad_rho: bool = True, want_D: bool = False, ws: torch.Tensor | None = None,
+                prepared: bool = False, want_stats: bool = False, stream=None) -> LogLik:
+    _events(events)
+    _need(rho, "rho", torch.float32, g.shape)
+    if s is not None:
+        _need(s, "s", torch.float32, g.shape)
+    n = events.shape[0]
+    if ws is None:
+        ws = workspace(g, n, rho.device)
+        prepared = False
+    out3 = torch.zeros(3, dtype=torch.float64, device=rho.device)
+    gr = torch.empty(g.shape, dtype=torch.float32, device=rho.device) if want_grad_rho else None
+    D = torch.empty(n, dtype=torch.float32, device=rho.device) if want_D else None
+    sm = (ctypes.c_double * 2)(*sigma_mask) if sigma_mask is not None else None
+    st = Stats() if want_stats else None
+    rc = _lib().jpet_loglik_grad(ctypes.byref(g), sm, _ptr(events), n, _ptr(s), _ptr(rho), _ptr(out3), _ptr(gr),
+                                 _ptr(D), _ptr(ws), ws.numel(), JPET_WS_PREPARED if prepared else 0,
+                                 ctypes.byref(st) if st is not None else None, _stream(stream))
+    if rc != JPET_EDOMAIN:
+        _check(rc, "jpet_loglik_grad")
+    return LogLik(out3, gr, D, st.as_dict() if st is not None else None)

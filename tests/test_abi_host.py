@@ -1,0 +1,113 @@
+"""Host-side checks of libjpet that need no GPU: the library loads, exports every symbol that
+include/jpet.h declares, and validates arguments before touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1502_07478_amd import jpet
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "jpet.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(jpet_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(jpet.LIB_PATH):
+        from paper_1502_07478_amd import build
+        build.build()
+    return jpet.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "jpet_mlem_iterate" in names and "jpet_sensitivity" in names and "jpet_loglik_grad" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_abi_version_and_strerror(lib):
+    assert lib.jpet_abi_version() == 1
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.jpet_strerror(code)
+    assert lib.jpet_strerror(-99) == b"unknown status"
+
+
+def ws_size(g, n):
+    b = ctypes.c_size_t(0)
+    rc = jpet.lib().jpet_mlem_workspace_size(ctypes.byref(g) if g is not None else None, n, ctypes.byref(b))
+    return rc, b.value
+
+
+GOOD = dict(R=450.0, L=500.0, sigma_z=10.0, sigma_dl=63.0, pixel=2.0, n_y=400, n_z=400)
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(R=0.0), jpet.JPET_EDOMAIN),
+    (dict(R=float("nan")), jpet.JPET_EDOMAIN),
+    (dict(L=-1.0), jpet.JPET_EDOMAIN),
+    (dict(sigma_z=0.0), jpet.JPET_EDOMAIN),
+    (dict(sigma_dl=float("inf")), jpet.JPET_EDOMAIN),
+    (dict(pixel=0.0), jpet.JPET_EDOMAIN),
+    (dict(n_y=0), jpet.JPET_EDOMAIN),
+    (dict(n_z=-5), jpet.JPET_EDOMAIN),
+    (dict(n_y=40000), jpet.JPET_EDOMAIN),
+    (dict(pixel=2.25), jpet.JPET_EDOMAIN),          # grid reaches |y| >= R
+    (dict(kernel_variant=2), jpet.JPET_EDOMAIN),
+    (dict(gamma=0.001), jpet.JPET_ENOTSUP),
+])
+def test_geometry_validation(lib, over, code):
+    g = jpet.geometry(**{**GOOD, **over})
+    assert ws_size(g, 10)[0] == code
+
+
+def test_workspace_size_grows_with_events(lib):
+    g = jpet.geometry(**GOOD)
+    rc0, b0 = ws_size(g, 0)
+    rc1, b1 = ws_size(g, 1000)
+    assert rc0 == 0 and rc1 == 0 and b1 > b0 > 0
+    assert ws_size(g, -1)[0] == jpet.JPET_EINVAL
+    assert ws_size(None, 10)[0] == jpet.JPET_EINVAL
+
+
+def test_entry_points_reject_bad_arguments_before_any_device_work(lib):
+    g = jpet.geometry(**GOOD)
+    gp = ctypes.byref(g)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    aligned_ws = ctypes.c_void_p(0x100000)
+    assert lib.jpet_sensitivity(gp, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_sensitivity(None, fake, None) == jpet.JPET_EINVAL
+    # negative event count, NULL events with n > 0, NULL rho, negative iterations, unknown flags
+    assert lib.jpet_mlem_iterate(gp, fake, -1, None, fake, 1, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_iterate(gp, None, 5, None, fake, 1, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_iterate(gp, fake, 5, None, None, 1, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_iterate(gp, fake, 5, None, fake, -1, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_iterate(gp, fake, 5, None, fake, 1, aligned_ws, 1 << 40, 8, None, None) == jpet.JPET_EINVAL
+    # workspace: NULL, misaligned, too small
+    assert lib.jpet_mlem_iterate(gp, fake, 5, None, fake, 1, None, 1 << 40, 0, None, None) == jpet.JPET_EWORKSPACE
+    assert lib.jpet_mlem_iterate(gp, fake, 5, None, fake, 1, ctypes.c_void_p(0x100004), 1 << 40, 0, None,
+                                 None) == jpet.JPET_EWORKSPACE
+    assert lib.jpet_mlem_iterate(gp, fake, 5, None, fake, 1, aligned_ws, 16, 0, None, None) == jpet.JPET_EWORKSPACE
+    assert lib.jpet_mlem_prepare(gp, fake, 5, aligned_ws, 16, None) == jpet.JPET_EWORKSPACE
+    # log-likelihood: NULL out3, bad mask sigma
+    assert lib.jpet_loglik_grad(gp, None, fake, 5, None, fake, None, None, None, aligned_ws, 1 << 40, 0, None,
+                                None) == jpet.JPET_EINVAL
+    bad_mask = (ctypes.c_double * 2)(0.0, 63.0)
+    assert lib.jpet_loglik_grad(gp, bad_mask, fake, 5, None, fake, fake, None, None, aligned_ws, 1 << 40, 0, None,
+                                None) == jpet.JPET_EDOMAIN
+
+
+def test_binding_requires_built_library(monkeypatch, tmp_path):
+    """The binding fails loudly (no fallback) when the library is missing."""
+    monkeypatch.setattr(jpet, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(jpet, "_L", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        jpet.lib()

@@ -1,0 +1,278 @@
+"""Parity of the HIP path (through the C-ABI) with the double-precision oracle.
+
+Tolerances (FP32 GPU against FP64 oracle):
+  sensitivity: max relative error 1e-6 (evaluated in double precision, rounded to float)
+  one MLEM step from the same input image: relative L2 1e-4
+  pair / valid / dropped counts: exact
+  log-likelihood: relative 1e-6; grad rho: relative L2 1e-4; grad sigma: relative 1e-3
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from jpet_synth import get_workload
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1502_07478_amd import jpet  # noqa: E402
+
+DEV = "cuda"
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def geoms(w, **over):
+    kw = w.geometry(**over)
+    return jpet.geometry(**kw), oracle.geometry(**kw)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = get_workload("tiny")
+    ev = w.events()
+    return w, ev, torch.from_numpy(ev).to(DEV)
+
+
+def test_sensitivity_matches_oracle(tiny):
+    w, _, _ = tiny
+    for over in ({}, dict(n_y=400, n_z=400, pixel=2.0), dict(L=1000.0, n_y=256, n_z=300, pixel=1.7)):
+        g, go = geoms(w, **over)
+        got = jpet.sensitivity(g).double().cpu().numpy()
+        want = oracle.sensitivity(go)
+        assert np.array_equal(got == 0, want == 0)
+        pos = want > 0
+        assert np.max(np.abs(got[pos] / want[pos] - 1)) <= 1e-6
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("with_s", [True, False])
+def test_tiny_each_step_from_the_oracle_iterate(tiny, variant, with_s):
+    """Every one of 5 iterations, started from the oracle's own iterate, within 1e-4 rel L2."""
+    w, ev_np, ev = tiny
+    g, go = geoms(w, kernel_variant=variant)
+    so = oracle.sensitivity(go)
+    s = jpet.sensitivity(g)
+    rho_o = oracle.initial_image(so) if with_s else so * oracle.initial_image(so)
+    for it in range(w.n_iter):
+        nxt, sto = oracle.mlem(go, ev_np, rho_o, 1, s=so if with_s else None)
+        rho = torch.from_numpy(rho_o.astype(np.float32)).to(DEV)
+        st = jpet.mlem_iterate(g, ev, rho, 1, s=s if with_s else None, want_stats=True)
+        got = rho.double().cpu().numpy()
+        assert rel_l2(got, nxt) <= 1e-4, (it, rel_l2(got, nxt))
+        for key in ("n_valid", "n_dropped", "n_pairs", "n_zero_denominator", "n_kappa_nonpositive"):
+            assert st[key] == sto[key], (key, st[key], sto[key])
+        rho_o = nxt
+
+
+def test_tiny_trajectory(tiny):
+    """Five GPU iterations in one call against five oracle iterations (drift stays small)."""
+    w, ev_np, ev = tiny
+    g, go = geoms(w)
+    so = oracle.sensitivity(go)
+    s = jpet.sensitivity(g)
+    rho = (s > 0).to(torch.float32)
+    jpet.mlem_iterate(g, ev, rho, w.n_iter, s=s)
+    want, _ = oracle.mlem(go, ev_np, oracle.initial_image(so), w.n_iter, s=so)
+    assert rel_l2(rho.cpu().numpy(), want) <= w.n_iter * 1e-4
+
+
+def test_prepared_workspace_reuse_gives_same_result(tiny):
+    w, _, ev = tiny
+    g, _ = geoms(w)
+    s = jpet.sensitivity(g)
+    ws = jpet.workspace(g, ev.shape[0])
+    jpet.prepare(g, ev, ws)
+    a = (s > 0).to(torch.float32)
+    b = a.clone()
+    jpet.mlem_iterate(g, ev, a, 2, s=s, ws=ws, prepared=True)
+    jpet.mlem_iterate(g, ev, b, 2, s=s)
+    torch.cuda.synchronize()
+    assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-6
+
+
+def test_count_conservation_gpu(tiny):
+    w, _, ev = tiny
+    g, _ = geoms(w)
+    s = jpet.sensitivity(g)
+    rho = (s > 0).to(torch.float32)
+    for _ in range(3):
+        st = jpet.mlem_iterate(g, ev, rho, 1, s=s, want_stats=True)
+        total = float((s.double() * rho.double()).sum())
+        assert total == pytest.approx(st["n_valid"] - st["n_zero_denominator"], rel=1e-5)
+
+
+# ---------------------------------------------------------------------------------------------
+# edge cases
+
+
+def run_both(g, go, ev_np, rho0, n_iter=1, with_s=True):
+    so = oracle.sensitivity(go)
+    s = jpet.sensitivity(g)
+    ev = torch.from_numpy(np.ascontiguousarray(ev_np, dtype=np.float32).reshape(-1, 3)).to(DEV)
+    rho = torch.from_numpy(np.asarray(rho0, dtype=np.float32)).to(DEV).contiguous()
+    st = jpet.mlem_iterate(g, ev, rho, n_iter, s=s if with_s else None, want_stats=True)
+    want, sto = oracle.mlem(go, ev_np, rho0, n_iter, s=so if with_s else None)
+    return rho.double().cpu().numpy(), want, st, sto
+
+
+def test_no_events(tiny):
+    w, _, _ = tiny
+    g, go = geoms(w)
+    got, want, st, sto = run_both(g, go, np.zeros((0, 3), np.float32), np.ones((64, 64)))
+    assert np.all(got == 0) and np.all(want == 0)
+    assert st["n_events"] == 0 and st["n_valid"] == 0
+
+
+def test_all_events_invalid(tiny):
+    w, _, _ = tiny
+    g, go = geoms(w)
+    ev = np.array([[300.0, 0.0, 0.0], [np.nan, 1.0, 2.0], [0.0, 0.0, 5000.0], [np.inf, 0, 0]], np.float32)
+    got, want, st, sto = run_both(g, go, ev, np.ones((64, 64)))
+    assert st["n_dropped"] == 4 == sto["n_dropped"]
+    assert np.all(got == 0)
+
+
+def test_single_event_and_ragged_grid(tiny):
+    w, ev_np, _ = tiny
+    # non-square grid whose column count is not a multiple of anything convenient
+    g, go = geoms(w, n_y=37, n_z=53, pixel=3.3)
+    for k in (1, 7, 129, 1000):
+        got, want, st, sto = run_both(g, go, ev_np[:k], np.ones((37, 53)))
+        assert st["n_pairs"] == sto["n_pairs"] and st["n_valid"] == sto["n_valid"]
+        if sto["n_valid"]:
+            assert rel_l2(got, want) <= 1e-4
+
+
+def test_zero_denominator_events_are_skipped(tiny):
+    w, ev_np, _ = tiny
+    g, go = geoms(w)
+    rho0 = np.zeros((64, 64))
+    rho0[40:48, 10:20] = 1.0
+    got, want, st, sto = run_both(g, go, ev_np[:3000], rho0)
+    assert st["n_zero_denominator"] == sto["n_zero_denominator"] > 0
+    assert rel_l2(got, want) <= 1e-4
+
+
+def test_events_at_grid_and_strip_edges(tiny):
+    w, _, _ = tiny
+    g, go = geoms(w)
+    rng = np.random.default_rng(3)
+    ev = np.stack([rng.uniform(-250, 250, 4000), rng.uniform(-250, 250, 4000), rng.uniform(-700, 700, 4000)], 1)
+    ev[:500, 0] = 250.0
+    ev[500:1000, 1] = -250.0
+    got, want, st, sto = run_both(g, go, ev.astype(np.float32), np.ones((64, 64)))
+    assert st["n_valid"] == sto["n_valid"] and st["n_pairs"] == sto["n_pairs"]
+    assert rel_l2(got, want) <= 1e-4
+
+
+def test_long_rows_and_many_rows():
+    """sigma large against the pixel: rows longer than a wavefront and more than 64 rows per event."""
+    from jpet_synth import Workload
+    w = Workload("wide", 450.0, 500.0, 15.0, 90.0, 1.171875, 512, 512, 3000, 1, 7, "c1")
+    g, go = geoms(w)
+    ev_np = w.events()
+    got, want, st, sto = run_both(g, go, ev_np, np.ones((512, 512)))
+    assert st["n_pairs"] == sto["n_pairs"]
+    assert rel_l2(got, want) <= 1e-4
+
+
+# ---------------------------------------------------------------------------------------------
+# production size (10M events, 400x400): sampled outputs and invariants
+
+
+@pytest.fixture(scope="module")
+def prod():
+    w = get_workload("prod400")
+    ev_np = w.events()
+    return w, ev_np, torch.from_numpy(ev_np).to(DEV)
+
+
+def test_prod400_sampled_parity(prod):
+    w, ev_np, ev = prod
+    g, go = geoms(w)
+    s = jpet.sensitivity(g)
+    so = oracle.sensitivity(go)
+    rho0 = (s > 0).to(torch.float32)
+    ws = jpet.workspace(g, ev.shape[0])
+    jpet.prepare(g, ev, ws)
+    rho = rho0.clone()
+    st = jpet.mlem_iterate(g, ev, rho, 1, s=s, ws=ws, prepared=True, want_stats=True)
+    # exact counts against a sample: the per-event pixel count of the oracle on 2000 events
+    rng = np.random.default_rng(0)
+    sel = rng.choice(len(ev_np), 2000, replace=False)
+    Do, cnt = oracle.denominators_at(go, ev_np, oracle.initial_image(so).ravel(), sel)
+    ll = jpet.loglik_grad(g, ev, rho0, s=s, want_grad_rho=False, want_D=True, ws=ws, prepared=True)
+    Dg = ll.D.double().cpu().numpy()[sel]
+    norm = (1 / 10.0 ** 2) * (1 / 63.0) / (2 * math.pi)
+    ok = Do > 0
+    np.testing.assert_allclose(Dg[ok], Do[ok], rtol=2e-5)
+    # count conservation over the whole image
+    total = float((s.double() * rho.double()).sum())
+    assert total == pytest.approx(st["n_valid"] - st["n_zero_denominator"], rel=1e-5)
+    # the new image at sampled pixels (every event touching them, in double precision)
+    pix = np.array([200 * 400 + 200, 150 * 400 + 180, 260 * 400 + 230, 330 * 400 + 160])
+    acc = oracle.backprojection_at(go, ev_np, oracle.initial_image(so).ravel(), pix)
+    got = rho.double().cpu().numpy().ravel()[pix] * so.ravel()[pix]
+    np.testing.assert_allclose(got, acc, rtol=1e-4)
+    assert norm > 0
+
+
+# ---------------------------------------------------------------------------------------------
+# log-likelihood and gradient
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_loglik_and_gradients_match_oracle(tiny, variant):
+    w, ev_np, ev = tiny
+    g, go = geoms(w, kernel_variant=variant)
+    so = oracle.sensitivity(go)
+    rho_o, _ = oracle.mlem(go, ev_np, oracle.initial_image(so), 2, s=so)
+    rho = torch.from_numpy(rho_o.astype(np.float32)).to(DEV)
+    s = jpet.sensitivity(g)
+    res = jpet.loglik_grad(g, ev, rho, s=s, want_D=True, want_stats=True)
+    l, dz, dd, gr, sto, D = oracle.loglik_grad(go, ev_np, rho.double().cpu().numpy(), s=so, return_D=True)
+    v = res.value.cpu().numpy()
+    assert v[0] == pytest.approx(l, rel=1e-6)
+    assert v[1] == pytest.approx(dz, rel=1e-3)
+    assert v[2] == pytest.approx(dd, rel=1e-3)
+    assert rel_l2(res.grad_rho.cpu().numpy(), gr) <= 1e-4
+    np.testing.assert_allclose(res.D.double().cpu().numpy(), D, rtol=2e-5, atol=1e-30)
+    assert res.stats["n_pairs"] == sto["n_pairs"]
+
+
+def test_loglik_sigma_gradient_matches_gpu_finite_differences(tiny):
+    w, ev_np, ev = tiny
+    g, go = geoms(w)
+    so = oracle.sensitivity(go)
+    rho_o, _ = oracle.mlem(go, ev_np, oracle.initial_image(so), 2, s=so)
+    rho = torch.from_numpy(rho_o.astype(np.float32)).to(DEV)
+    s = jpet.sensitivity(g)
+    base = jpet.loglik_grad(g, ev, rho, s=s, want_grad_rho=False).value.cpu().numpy()
+    mask = (w.sigma_z, w.sigma_dl)
+
+    def ll(sz, sd):
+        gg = jpet.geometry(**w.geometry(sigma_z=sz, sigma_dl=sd))
+        return jpet.loglik_grad(gg, ev, rho, s=s, sigma_mask=mask, want_grad_rho=False).value.cpu().numpy()[0]
+
+    hz, hd = 1e-3 * w.sigma_z, 1e-3 * w.sigma_dl
+    fd_z = (ll(w.sigma_z + hz, w.sigma_dl) - ll(w.sigma_z - hz, w.sigma_dl)) / (2 * hz)
+    fd_d = (ll(w.sigma_z, w.sigma_dl + hd) - ll(w.sigma_z, w.sigma_dl - hd)) / (2 * hd)
+    assert base[1] == pytest.approx(fd_z, rel=1e-3)
+    assert base[2] == pytest.approx(fd_d, rel=1e-3)
+
+
+def test_loglik_zero_denominator_is_minus_infinity(tiny):
+    w, ev_np, ev = tiny
+    g, _ = geoms(w)
+    rho = torch.zeros(g.shape, device=DEV)
+    res = jpet.loglik_grad(g, ev, rho, want_grad_rho=False, want_stats=True)
+    assert res.value[0].item() == -math.inf
+    assert res.stats["n_zero_denominator"] == res.stats["n_valid"]
