@@ -88,11 +88,15 @@ typedef struct jpet_stats {
   int64_t n_zero_denominator;
   int64_t n_pairs;             /* (valid event, in-ellipse pixel) pairs per iteration */
   int64_t n_kappa_nonpositive; /* in-ellipse pairs whose Eq. 7 denominator term is <= 0 (P := 0) */
+  int64_t n_unplaced_rows;     /* ellipse rows the binned event pass could not place in its
+                                  workgroup's region (last iteration); always 0 unless the
+                                  library is faulty -- such rows are skipped, not written */
 } jpet_stats;
 
 /* Flags for jpet_mlem_iterate and jpet_loglik_grad. */
 #define JPET_WS_PREPARED 1u /* the workspace already holds jpet_mlem_prepare's output for
-                               exactly this geometry and event array; skip that step */
+                               exactly this geometry, event array and event count (for
+                               jpet_loglik_grad: prepared with the mask's sigmas); skip that step */
 
 /* Text for a status code (static storage, never NULL). */
 const char* jpet_strerror(int status);
@@ -148,11 +152,20 @@ int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, co
  *   grad_rho: device float [n_y*n_z] or NULL
  *   D_out:    device float [n] per-event D_j (0 for dropped events) or NULL
  *   s:        as for jpet_mlem_iterate (NULL = 1)
- * Returns JPET_EDOMAIN (after writing l = -inf) when a valid event has D_j = 0; this case
- * synchronises the stream to read the count. */
+ * When a valid event has D_j = 0 the device value l is -inf; if stats is given (the call then
+ * synchronises) the call also returns JPET_EDOMAIN in that case. */
 int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const float* events, int64_t n,
                      const float* s, const float* rho, double* out3, float* grad_rho, float* D_out, void* ws,
                      size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream);
+
+/* Kernel timing.  While enabled (enable != 0), every launch of the MLEM event pass made by
+ * jpet_mlem_iterate is bracketed by a pair of HIP events recorded on the caller's stream (the
+ * stream the kernel runs on).  jpet_profile_read waits for the recorded events, writes the
+ * number of timed launches and their summed duration in milliseconds (host outputs, nullable)
+ * and forgets them.  Disabling also forgets unread timings.  Process-wide, thread-safe; the
+ * events are host-side objects, no device memory is allocated. */
+int jpet_profile_enable(int enable);
+int jpet_profile_read(int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus
 }

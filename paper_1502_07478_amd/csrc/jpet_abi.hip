@@ -4,6 +4,10 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "jpet_internal.h"
 
 namespace jpet {
@@ -11,6 +15,19 @@ namespace jpet {
 namespace {
 
 thread_local int g_last_hip_error = 0;
+
+// event-pass timing (jpet_profile_enable / jpet_profile_read)
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
+
+void prof_forget_locked() {
+  for (auto& pr : g_prof_events) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  g_prof_events.clear();
+}
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -43,6 +60,7 @@ Geo make_geo(const jpet_geometry* g, double mask_sz, double mask_sdl) {
   o.sigma_z = g->sigma_z;
   o.sigma_dl = g->sigma_dl;
   o.pixel = g->pixel;
+  o.ipix = 1.0 / g->pixel;
   o.u = 1.0 / (g->sigma_z * g->sigma_z);
   o.w = 1.0 / (g->sigma_dl * g->sigma_dl);
   o.um = 1.0 / (mask_sz * mask_sz);
@@ -57,10 +75,10 @@ Geo make_geo(const jpet_geometry* g, double mask_sz, double mask_sdl) {
 
 int64_t npix_of(const jpet_geometry* g) { return (int64_t)g->n_y * (int64_t)g->n_z; }
 
-int carve(const jpet_geometry* g, int64_t n, void* ws, size_t ws_bytes, Workspace* out) {
+int carve(const Plan& p, const jpet_geometry* g, int64_t n, void* ws, size_t ws_bytes, Workspace* out) {
   if (!ws) return JPET_EWORKSPACE;
   if (((uintptr_t)ws & 255) != 0) return JPET_EWORKSPACE;
-  size_t need = workspace_layout(n, npix_of(g), ws, out);
+  size_t need = workspace_layout(p, n, npix_of(g), ws, out);
   if (ws_bytes < need) return JPET_EWORKSPACE;
   return JPET_OK;
 }
@@ -77,31 +95,135 @@ int read_stats(const Workspace& ws, int64_t n, jpet_stats* stats, hipStream_t st
   stats->n_zero_denominator = (int64_t)c[C_ZERO_DEN];
   stats->n_pairs = (int64_t)c[C_PAIRS];
   stats->n_kappa_nonpositive = (int64_t)c[C_KAPPA_BAD];
+  stats->n_unplaced_rows = (int64_t)c[C_OUTSIDE];
   return JPET_OK;
 }
 
-int do_prepare(const Geo& geo, const float* events, int64_t n, const Workspace& w, hipStream_t st) {
+int do_prepare(const Geo& geo, const Plan& p, const float* events, int64_t n, const Workspace& w, hipStream_t st) {
   hipError_t e = launch_fill_u64(w.cnt, C_COUNT, st);
   if (e != hipSuccess) return hip_fail(e);
-  e = launch_prepare(geo, events, n, w, st);
+  e = launch_prepare(geo, p, events, n, w, st);
   if (e != hipSuccess) return hip_fail(e);
   return JPET_OK;
 }
 
 }  // namespace
 
-size_t workspace_layout(int64_t n, int64_t npix, void* base, Workspace* out) {
+Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n) {
+  Plan p;
+  memset(&p, 0, sizeof(p));
+  p.ntb = 1;
+  p.dt = 1.0;
+  const double pix = g->pixel;
+  const double hy_px = 1.5 * mdl / pix;                 // largest half height of an ellipse (rows)
+  const double chord_px = 2.0 * 3.0 * msz / sqrt(2.0) / pix;  // longest chord along z (columns)
+  const int maxrow = (int)floor(chord_px) + 1;
+  const int rows_max = (int)floor(2.0 * hy_px) + 1;
+  const double tmax = 0.5 * g->L / g->R;               // |tan| of any valid event
+  int maxlen = 0;
+  for (int c : {16, 32, 48, 64})
+    if (maxrow <= c) {
+      maxlen = c;
+      break;
+    }
+  const int waves = 16;
+  const int ev_per_batch = rows_max > 0 ? (64 * waves) / rows_max : 0;
+  const size_t lds_budget = 150 * 1024;
+  if (maxlen == 0 || ev_per_batch < 1) return p;  // generic pass
+  p.maxlen = maxlen;
+  p.waves = waves;
+  p.ev_per_batch = ev_per_batch < 64 ? ev_per_batch : 64;
+  p.HY = (int)ceil(hy_px + 0.5) + 1;
+  // candidates: no shear, then t bins of decreasing width; tiles of decreasing size
+  const double dts[] = {0.0, 0.4, 0.2, 0.1, 0.05, 0.025};
+  const int tiles[] = {32, 24, 16, 12, 8};
+  bool found = false;
+  for (double dt : dts) {
+    // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
+    const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
+    const double hz = 3.0 * sqrt(0.5 * msz * msz + 0.25 * mdl * mdl * tau * tau);
+    const int HZ = (int)ceil(hz / pix + 1.0) + 1;
+    for (int T : tiles) {
+      const int RY = T + 2 * p.HY, W = T + 2 * HZ;
+      const size_t bytes = (size_t)RY * (size_t)W * 12u;
+      if (bytes > lds_budget) continue;
+      p.TY = T;
+      p.TZ = T;
+      p.HZ = HZ;
+      p.RY = RY;
+      p.W = W;
+      p.lds_bytes = bytes;
+      if (dt == 0.0) {
+        p.ntb = 1;
+        p.tmin = 0.0;
+        p.dt = 1.0;
+      } else {
+        p.ntb = (int)ceil(2.0 * tmax / dt);
+        if (p.ntb < 1) p.ntb = 1;
+        p.dt = dt;
+        p.tmin = -0.5 * dt * p.ntb;
+      }
+      found = true;
+      break;
+    }
+    if (found) break;
+  }
+  if (!found) {
+    memset(&p, 0, sizeof(p));
+    p.ntb = 1;
+    p.dt = 1.0;
+    return p;
+  }
+  p.nty = (g->n_y + p.TY - 1) / p.TY;
+  // sheared column span: the widest over the t bins
+  int span = g->n_z;
+  for (int b = 0; b < p.ntb; ++b) {
+    const double tc = p.ntb > 1 ? p.tmin + (b + 0.5) * p.dt : 0.0;
+    const double y0 = (0.5 - 0.5 * (double)g->n_y) * pix, y1 = y0 + (g->n_y - 1) * pix;
+    const int o0 = (int)rint(tc * y0 / pix), o1 = (int)rint(tc * y1 / pix);
+    const int lo = o0 < o1 ? o0 : o1, hi = o0 < o1 ? o1 : o0;
+    const int sp = g->n_z + (hi - lo);
+    if (sp > span) span = sp;
+  }
+  p.ntz = (span + p.TZ - 1) / p.TZ;
+  p.nbins = p.ntb * p.nty * p.ntz;
+  // events per workgroup item: enough items to fill the chip, at most 32 batches
+  int64_t per = n / 1024;
+  if (per < p.ev_per_batch) per = p.ev_per_batch;
+  if (per > 32 * p.ev_per_batch) per = 32 * p.ev_per_batch;
+  p.ev_per_wg = (int)((per / p.ev_per_batch) * p.ev_per_batch);
+  const int64_t nonempty = n < p.nbins ? n : p.nbins;
+  p.max_items = (n + p.ev_per_wg - 1) / p.ev_per_wg + nonempty;
+  if (p.max_items < 1) p.max_items = 1;
+  p.tiled = 1;
+  return p;
+}
+
+size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Workspace* out) {
   size_t off = 0;
   char* b = (char*)base;
+  auto take = [&](size_t bytes) {
+    char* q = b + off;
+    off = align_up(off + bytes, 256);
+    return q;
+  };
+  const size_t nn = (size_t)(n > 0 ? n : 0);
+  const size_t nb = (size_t)(p.tiled ? p.nbins : 0);
   Workspace w;
-  w.ev = (EventRec*)(b + off);
-  off = align_up(off + sizeof(EventRec) * (size_t)(n > 0 ? n : 0), 256);
-  w.cnt = (unsigned long long*)(b + off);
-  off = align_up(off + sizeof(unsigned long long) * C_COUNT, 256);
-  w.acc = (float*)(b + off);
-  off = align_up(off + sizeof(float) * (size_t)npix, 256);
-  w.red = (double*)(b + off);
-  off = align_up(off + sizeof(double) * RED_SLOTS, 256);
+  // buffers every entry point uses come first, so their offsets do not depend on the binning
+  w.cnt = (unsigned long long*)take(sizeof(unsigned long long) * C_COUNT);
+  w.red = (double*)take(sizeof(double) * RED_SLOTS);
+  w.acc = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)npix);
+  w.B = (double*)take(sizeof(double) * (size_t)npix);
+  w.ev = (EventRec*)take(sizeof(EventRec) * nn);
+  w.key = (uint32_t*)take(sizeof(uint32_t) * nn);
+  // binning (tiled pass only)
+  w.evs = (EventRec*)take(p.tiled ? sizeof(EventRec) * nn : 0);
+  w.bin_count = (uint32_t*)take(sizeof(uint32_t) * nb);
+  w.bin_start = (uint32_t*)take(sizeof(uint32_t) * (nb + 1));
+  w.bin_fill = (uint32_t*)take(sizeof(uint32_t) * nb);
+  w.item_start = (uint32_t*)take(sizeof(uint32_t) * (nb + 1));
+  w.items = (BinItem*)take(p.tiled ? sizeof(BinItem) * (size_t)p.max_items : 0);
   w.bytes = off;
   if (out) *out = w;
   return off;
@@ -129,6 +251,30 @@ int jpet_last_hip_error(void) { return g_last_hip_error; }
 
 int jpet_abi_version(void) { return JPET_ABI_VERSION; }
 
+int jpet_profile_enable(int enable) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = enable != 0;
+  if (!g_prof_on) prof_forget_locked();
+  return JPET_OK;
+}
+
+int jpet_profile_read(int64_t* launches, double* total_ms) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double tot = 0.0;
+  int rc = JPET_OK;
+  for (auto& pr : g_prof_events) {
+    hipError_t e = hipEventSynchronize(pr.second);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess && rc == JPET_OK) rc = hip_fail(e);
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)g_prof_events.size();
+  if (total_ms) *total_ms = tot;
+  prof_forget_locked();
+  return rc;
+}
+
 int jpet_sensitivity(const jpet_geometry* g, float* s_out, void* stream) {
   int rc = check_geometry(g);
   if (rc) return rc;
@@ -143,7 +289,8 @@ int jpet_mlem_workspace_size(const jpet_geometry* g, int64_t n_events, size_t* b
   int rc = check_geometry(g);
   if (rc) return rc;
   if (!bytes || n_events < 0) return JPET_EINVAL;
-  *bytes = workspace_layout(n_events, npix_of(g), nullptr, nullptr);
+  const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n_events);
+  *bytes = workspace_layout(p, n_events, npix_of(g), nullptr, nullptr);
   return JPET_OK;
 }
 
@@ -152,10 +299,11 @@ int jpet_mlem_prepare(const jpet_geometry* g, const float* events, int64_t n, vo
   int rc = check_geometry(g);
   if (rc) return rc;
   if (n < 0 || (n > 0 && !events)) return JPET_EINVAL;
+  const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
   Workspace w;
-  rc = carve(g, n, ws, ws_bytes, &w);
+  rc = carve(p, g, n, ws, ws_bytes, &w);
   if (rc) return rc;
-  return do_prepare(make_geo(g, g->sigma_z, g->sigma_dl), events, n, w, (hipStream_t)stream);
+  return do_prepare(make_geo(g, g->sigma_z, g->sigma_dl), p, events, n, w, (hipStream_t)stream);
 }
 
 int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, const float* s, float* rho,
@@ -165,23 +313,40 @@ int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, co
   if (rc) return rc;
   if (n < 0 || (n > 0 && !events) || !rho || n_iter < 0) return JPET_EINVAL;
   if (flags & ~JPET_WS_PREPARED) return JPET_EINVAL;
+  const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
   Workspace w;
-  rc = carve(g, n, ws, ws_bytes, &w);
+  rc = carve(p, g, n, ws, ws_bytes, &w);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   const Geo geo = make_geo(g, g->sigma_z, g->sigma_dl);
   if (!(flags & JPET_WS_PREPARED)) {
-    rc = do_prepare(geo, events, n, w, st);
+    rc = do_prepare(geo, p, events, n, w, st);
     if (rc) return rc;
   }
-  hipError_t e = launch_fill_f32(w.acc, npix_of(g), st);
+  hipError_t e = launch_fill_u64(w.acc, npix_of(g), st);
   if (e != hipSuccess) return hip_fail(e);
   for (int it = 0; it < n_iter; ++it) {
-    // per-iteration counters: zero-denominator events and non-positive kappa pairs
+    // per-iteration counters: zero-denominator events, non-positive kappa pairs, unplaced rows
     e = launch_fill_u64(w.cnt + C_ZERO_DEN, 2, st);
     if (e != hipSuccess) return hip_fail(e);
-    e = launch_event_pass(geo, n, w, rho, st);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      timed = g_prof_on;
+    }
+    if (timed) {
+      if ((e = hipEventCreate(&ev0)) != hipSuccess) return hip_fail(e);
+      if ((e = hipEventCreate(&ev1)) != hipSuccess) return hip_fail(e);
+      if ((e = hipEventRecord(ev0, st)) != hipSuccess) return hip_fail(e);
+    }
+    e = launch_event_pass(geo, p, n, w, rho, st);
     if (e != hipSuccess) return hip_fail(e);
+    if (timed) {
+      if ((e = hipEventRecord(ev1, st)) != hipSuccess) return hip_fail(e);
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      g_prof_events.emplace_back(ev0, ev1);
+    }
     e = launch_update(geo, s, rho, w, st);
     if (e != hipSuccess) return hip_fail(e);
   }
@@ -202,13 +367,16 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
     mdl = sigma_mask[1];
     if (!finite_pos(msz) || !finite_pos(mdl)) return JPET_EDOMAIN;
   }
+  // the gradient pass walks events in input order and needs no binning
+  Plan p = make_plan(g, msz, mdl, n);
+  p.tiled = 0;
   Workspace w;
-  rc = carve(g, n, ws, ws_bytes, &w);
+  rc = carve(p, g, n, ws, ws_bytes, &w);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   const Geo geo = make_geo(g, msz, mdl);
   if (!(flags & JPET_WS_PREPARED)) {
-    rc = do_prepare(geo, events, n, w, st);
+    rc = do_prepare(geo, p, events, n, w, st);
     if (rc) return rc;
   }
   hipError_t e = launch_fill_u64(w.cnt + C_ZERO_DEN, 2, st);

@@ -1,0 +1,139 @@
+// Device helpers shared by the libjpet kernels: the ellipse rows of an event and the kernel
+// P(e|i) along a pixel row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "jpet_internal.h"
+
+namespace jpet {
+
+constexpr int WAVE = 64;
+constexpr double kPi = 3.14159265358979323846;
+// exp(x) = exp2(x log2 e); the kernel's exponent is -(q - gamma^2 / kappa) / 2
+constexpr double kHalfLog2e = 0.72134752044448170368;
+// fixed-point unit of the back-projection accumulators: 2^-32
+constexpr float kFix = 4294967296.0f;
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+__device__ inline int wave_max_i(int v) {
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, WAVE));
+  return v;
+}
+
+// Column shift of row r in the frame sheared along slope tc (see Plan).
+__device__ inline int shear_offset(const Geo& g, double tc, int r) {
+  return (int)rint(tc * (g.y0 + (double)r * g.pixel) * g.ipix);
+}
+
+// Central slope of t bin b (0 when the binning has no shear).
+__device__ inline double bin_slope(const Plan& p, int b) {
+  return p.ntb > 1 ? p.tmin + ((double)b + 0.5) * p.dt : 0.0;
+}
+
+// Pixel columns [klo, khi] of row i inside the 3-sigma ellipse of event e, for the mask
+// resolution (um, wm).  In a row of fixed y the quadratic form b C^-1 b equals
+// 2 um b1^2 + 4 wm c^2 dy^2 with b1 = z - z~ - dy tan (Eq. 10-12), so the ellipse (Sec. 3) is the
+// interval |z - (z~ + dy tan)| <= sqrt((9 - 4 wm c^2 dy^2) / (2 um)).  Double precision, so the
+// pixel set is the one a per-pixel double-precision test b C^-1 b <= 9 selects.
+__device__ inline bool row_interval(const Geo& g, const EventRec& e, int i, int* klo, int* khi) {
+  const double Y = g.y0 + (double)i * g.pixel;
+  const double dy = Y - e.y;
+  const double c = e.c;
+  const double rem = 9.0 - 4.0 * g.wm * c * c * dy * dy;
+  if (!(rem >= 0.0)) return false;
+  const double H = sqrt(rem * (0.5 / g.um));
+  const double zc = e.z + e.t * dy;
+  double a = ceil((zc - H - g.z0) * g.ipix);
+  double b = floor((zc + H - g.z0) * g.ipix);
+  if (a < 0.0) a = 0.0;
+  if (b > (double)(g.n_z - 1)) b = (double)(g.n_z - 1);
+  if (a > b) return false;
+  *klo = (int)a;
+  *khi = (int)b;
+  return true;
+}
+
+// Single-precision constants of the kernel along one pixel row (Eq. 7-11 with gamma = 0).
+// With Y the row's y, dy = Y - y~ and b1 = z - z~ - dy tan the running coordinate:
+//   kappa = aC^-1a + 2 oC^-1b = 2u c^4 (R^2 + Y^2) + w fa^2 Y^2 c^2 t^2 + 4 w c^2 (1 + 2t^2) Y dy
+//                              - 4 u t c^2 Y b1
+//   gamma = bC^-1a           = 2 fa w c^2 t Y dy - 2 u c^2 Y b1
+//   q     = bC^-1b           = 2 u b1^2 + 4 w c^2 dy^2
+// and P / (u sqrt(w) / 2 pi) = kappa^-1/2 exp2(S (gamma^2 / kappa - q)) with S = log2(e) / 2.
+struct RowK {
+  float b10, pix;    // b1 at the row's first pixel and its step
+  float kap0, dkap;  // kappa at the first pixel and its step
+  float gs0, dgs;    // sqrt(S) gamma at the first pixel and its step
+  float a2, aq;      // S q = a2 b1^2 + aq
+};
+
+__device__ inline RowK row_constants(const Geo& g, const EventRec& e, int i, int klo, double* kap_first,
+                                     double* kap_step) {
+  const double Y = g.y0 + (double)i * g.pixel;
+  const double dy = Y - e.y;
+  const double t = e.t, c = e.c, c2 = c * c;
+  const double u = g.u, w = g.w, f = g.fa;
+  const double zc = e.z + t * dy;
+  const double b10 = g.z0 + (double)klo * g.pixel - zc;
+  const double kap_r = 2.0 * u * c2 * c2 * (g.R * g.R + Y * Y) + w * f * f * Y * Y * c2 * t * t +
+                       4.0 * w * c2 * (1.0 + 2.0 * t * t) * Y * dy;
+  const double kap_b = -4.0 * u * t * c2 * Y;
+  const double gam_r = 2.0 * f * w * c2 * t * Y * dy;
+  const double gam_b = -2.0 * u * c2 * Y;
+  const double rs = 0.84932180028801904272;  // sqrt(log2(e) / 2)
+  RowK r;
+  r.b10 = (float)b10;
+  r.pix = (float)g.pixel;
+  *kap_first = kap_r + kap_b * b10;
+  *kap_step = kap_b * g.pixel;
+  r.kap0 = (float)*kap_first;
+  r.dkap = (float)*kap_step;
+  r.gs0 = (float)(rs * (gam_r + gam_b * b10));
+  r.dgs = (float)(rs * gam_b * g.pixel);
+  r.a2 = (float)(kHalfLog2e * 2.0 * u);
+  r.aq = (float)(kHalfLog2e * 4.0 * w * c2 * dy * dy);
+  return r;
+}
+
+// P / (u sqrt(w) / 2 pi) at the j-th pixel of the row; kappa must be positive.
+__device__ inline float kernel_fast(const RowK& r, float jf) {
+  const float b1 = fmaf(jf, r.pix, r.b10);
+  const float kap = fmaf(jf, r.dkap, r.kap0);
+  const float gs = fmaf(jf, r.dgs, r.gs0);
+  const float rk = __builtin_amdgcn_rsqf(kap);
+  const float sq = fmaf(r.a2 * b1, b1, r.aq);
+  const float arg = fmaf(gs * gs, rk * rk, -sq);
+  return rk * __builtin_amdgcn_exp2f(arg);
+}
+
+// The same with the kappa <= 0 case (P := 0) handled per pixel.
+__device__ inline float kernel_guarded(const RowK& r, float jf, bool* bad) {
+  const float kap = fmaf(jf, r.dkap, r.kap0);
+  if (!(kap > 0.0f)) {
+    *bad = true;
+    return 0.0f;
+  }
+  return kernel_fast(r, jf);
+}
+
+}  // namespace jpet

@@ -1,113 +1,10 @@
-// gfx950 kernels of libjpet: sensitivity (Eq. 4), per-event preparation (Eq. 2, App. B),
-// the MLEM event pass (Eq. 7-12 inside the 3-sigma ellipse, Sec. 4 listing), the pixel
-// update (Eq. 3/5) and the log-likelihood / gradient pass.
-#include <hip/hip_runtime.h>
-#include <math.h>
-
-#include "jpet_internal.h"
+// gfx950 kernels of libjpet: sensitivity (Eq. 4), buffer fills and the log-likelihood /
+// gradient pass.
+#include "jpet_device.h"
 
 namespace jpet {
 
 namespace {
-
-constexpr int WAVE = 64;
-constexpr double kPi = 3.14159265358979323846;
-// exp(x) = exp2(x * log2(e)); the kernel's exponent is -1/2 (q - gamma^2 / kappa)
-constexpr double kHalfLog2e = 0.72134752044448170368;
-
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
-}
-
-__device__ inline double wave_sum_d(double v) {
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
-}
-
-__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
-}
-
-// Pixel columns of row i that lie inside the 3-sigma ellipse of event e (mask resolution).
-// In a row of fixed y, b C^-1 b = 2 u_m b1^2 + 4 w_m c^2 dy^2 with b1 = z - z~ - dy tan, so the
-// ellipse is the interval |z - (z~ + dy tan)| <= sqrt((9 - 4 w_m c^2 dy^2) / (2 u_m)).
-// Double precision, so that the pixel set matches a per-pixel test b C^-1 b <= 9.
-__device__ inline bool row_interval(const Geo& g, const EventRec& e, int i, int* klo, int* khi) {
-  const double Y = g.y0 + (double)i * g.pixel;
-  const double dy = Y - e.y;
-  const double c = e.c;
-  const double rem = 9.0 - 4.0 * g.wm * c * c * dy * dy;
-  if (!(rem >= 0.0)) return false;
-  const double H = sqrt(rem / (2.0 * g.um));
-  const double zc = e.z + e.t * dy;
-  double a = ceil((zc - H - g.z0) / g.pixel);
-  double b = floor((zc + H - g.z0) / g.pixel);
-  if (a < 0.0) a = 0.0;
-  if (b > (double)(g.n_z - 1)) b = (double)(g.n_z - 1);
-  if (a > b) return false;
-  *klo = (int)a;
-  *khi = (int)b;
-  return true;
-}
-
-// Row constants of the kernel (Eq. 7-11, gamma = 0) in single precision, for a row of fixed y.
-// With b1 = z - z~ - dy tan along the row and Y the pixel's y:
-//   kappa = aC^-1a + 2 oC^-1b = 2u c^4 (R^2 + Y^2) + w fa^2 Y^2 c^2 t^2 + 4 w c^2 (1 + 2t^2) Y dy
-//                              - 4 u t c^2 Y b1
-//   gamma = bC^-1a           = 2 fa w c^2 t Y dy - 2 u c^2 Y b1
-//   q     = bC^-1b           = 2 u b1^2 + 4 w c^2 dy^2
-// and P / (u sqrt(w) / 2 pi) = kappa^-1/2 exp2(S (gamma^2 / kappa - q)), S = log2(e) / 2.
-struct RowK {
-  float b10, pix;      // b1 at the first pixel, step of b1
-  float kap0, dkap;    // kappa at the first pixel, step
-  float gs0, dgs;      // sqrt(S) gamma at the first pixel, step
-  float a2, aq;        // S q = a2 b1^2 + aq
-};
-
-__device__ inline RowK row_constants(const Geo& g, const EventRec& e, int i, int klo) {
-  const double Y = g.y0 + (double)i * g.pixel;
-  const double dy = Y - e.y;
-  const double t = e.t, c = e.c, c2 = c * c;
-  const double u = g.u, w = g.w, f = g.fa;
-  const double zc = e.z + t * dy;
-  const double b10 = g.z0 + (double)klo * g.pixel - zc;
-  const double kap_r = 2.0 * u * c2 * c2 * (g.R * g.R + Y * Y) + w * f * f * Y * Y * c2 * t * t +
-                       4.0 * w * c2 * (1.0 + 2.0 * t * t) * Y * dy;
-  const double kap_b = -4.0 * u * t * c2 * Y;
-  const double gam_r = 2.0 * f * w * c2 * t * Y * dy;
-  const double gam_b = -2.0 * u * c2 * Y;
-  const double rs = sqrt(kHalfLog2e);
-  RowK r;
-  r.b10 = (float)b10;
-  r.pix = (float)g.pixel;
-  r.kap0 = (float)(kap_r + kap_b * b10);
-  r.dkap = (float)(kap_b * g.pixel);
-  r.gs0 = (float)(rs * (gam_r + gam_b * b10));
-  r.dgs = (float)(rs * gam_b * g.pixel);
-  r.a2 = (float)(kHalfLog2e * 2.0 * u);
-  r.aq = (float)(kHalfLog2e * 4.0 * w * c2 * dy * dy);
-  return r;
-}
-
-// Kernel value (without the constant u sqrt(w) / 2 pi) at the j-th pixel of the row.
-__device__ inline float kernel_at(const RowK& r, float jf, bool* bad) {
-  const float b1 = fmaf(jf, r.pix, r.b10);
-  const float kap = fmaf(jf, r.dkap, r.kap0);
-  const float gs = fmaf(jf, r.dgs, r.gs0);
-  if (!(kap > 0.0f)) {
-    *bad = true;
-    return 0.0f;
-  }
-  const float rk = __builtin_amdgcn_rsqf(kap);
-  const float sq = fmaf(r.a2 * b1, b1, r.aq);
-  const float arg = fmaf(gs * gs, rk * rk, -sq);
-  return rk * __builtin_amdgcn_exp2f(arg);
-}
 
 // ------------------------------------------------------------------------------------------
 
@@ -124,132 +21,14 @@ __global__ void k_sensitivity(Geo g, float* s) {
   }
 }
 
-// One thread per event: direct reconstruction (Eq. 2), ellipse rows (App. B), pixel count.
-__global__ void k_prepare(Geo g, const float* __restrict__ events, int64_t n, EventRec* __restrict__ ev,
-                          unsigned long long* __restrict__ cnt) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long valid = 0, pairs = 0;
-  if (j < n) {
-    const float zu = events[3 * j], zd = events[3 * j + 1], dl = events[3 * j + 2];
-    EventRec e;
-    e.r0 = 0;
-    e.r1 = -1;
-    e.npix = 0;
-    e.pad = 0;
-    e.t = e.c = e.y = e.z = 0.0;
-    const double hl = 0.5 * g.L;
-    if (isfinite(zu) && isfinite(zd) && isfinite(dl) && fabs((double)zu) <= hl && fabs((double)zd) <= hl) {
-      const double t = ((double)zu - (double)zd) / (2.0 * g.R);
-      const double c = sqrt(1.0 + t * t);
-      const double y = -0.5 * (double)dl / c;
-      const double z = 0.5 * ((double)zu + (double)zd + 2.0 * y * t);
-      e.t = t;
-      e.c = c;
-      e.y = y;
-      e.z = z;
-      // rows whose centre lies within the half height 1.5 sigma_dl / c of the ellipse
-      const double hy = 1.5 / (sqrt(g.wm) * c);
-      double a = ceil((y - hy - g.y0) / g.pixel);
-      double b = floor((y + hy - g.y0) / g.pixel);
-      if (a < 0.0) a = 0.0;
-      if (b > (double)(g.n_y - 1)) b = (double)(g.n_y - 1);
-      int first = 1 << 30, last = -1;
-      long long cntp = 0;
-      for (int i = (int)a; i <= (int)b && a <= b; ++i) {
-        int klo, khi;
-        if (row_interval(g, e, i, &klo, &khi)) {
-          if (first > i) first = i;
-          last = i;
-          cntp += khi - klo + 1;
-        }
-      }
-      if (cntp > 0) {
-        e.r0 = first;
-        e.r1 = last;
-        e.npix = (int)cntp;
-        valid = 1;
-        pairs = (unsigned long long)cntp;
-      }
-    }
-    ev[j] = e;
-  }
-  const unsigned long long v = wave_sum_u64(valid), p = wave_sum_u64(pairs),
-                           in = wave_sum_u64(j < n ? 1ull : 0ull);
-  if ((threadIdx.x & (WAVE - 1)) == 0 && in) {
-    atomicAdd(&cnt[C_VALID], v);
-    atomicAdd(&cnt[C_DROPPED], in - v);
-    atomicAdd(&cnt[C_PAIRS], p);
-  }
-}
-
-__global__ void k_fill_u64(unsigned long long* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0ull;
-}
-
-__global__ void k_fill_f32(float* p, int64_t n) {
+__global__ void k_fill_u64(unsigned long long* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0f;
+    p[i] = 0ull;
 }
 
-// One wavefront per event, one lane per ellipse row.  Pass 1 forms D = sum P rho, pass 2 adds
-// rho P / D into the accumulator image.
-__global__ void __launch_bounds__(256) k_event_pass(Geo g, int64_t n, const EventRec* __restrict__ ev,
-                                                    const float* __restrict__ rho, float* __restrict__ acc,
-                                                    unsigned long long* __restrict__ cnt) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t j = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
-  if (j >= n) return;
-  const EventRec e = ev[j];
-  if (e.r1 < e.r0) return;
-  bool bad = false;
-  float D = 0.0f;
-  for (int base = e.r0; base <= e.r1; base += WAVE) {
-    const int i = base + lane;
-    int klo, khi;
-    if (i <= e.r1 && row_interval(g, e, i, &klo, &khi)) {
-      const RowK r = row_constants(g, e, i, klo);
-      const float* rr = rho + (int64_t)i * g.n_z;
-      for (int k = klo; k <= khi; ++k) D += kernel_at(r, (float)(k - klo), &bad) * rr[k];
-    }
-  }
-  D = wave_sum(D);
-  const unsigned long long nbad = wave_sum_u64(bad ? 1ull : 0ull);
-  if (lane == 0 && nbad) atomicAdd(&cnt[C_KAPPA_BAD], nbad);
-  if (!(D > 0.0f)) {
-    if (lane == 0) atomicAdd(&cnt[C_ZERO_DEN], 1ull);
-    return;
-  }
-  const float invD = 1.0f / D;
-  for (int base = e.r0; base <= e.r1; base += WAVE) {
-    const int i = base + lane;
-    int klo, khi;
-    if (i <= e.r1 && row_interval(g, e, i, &klo, &khi)) {
-      const RowK r = row_constants(g, e, i, klo);
-      const float* rr = rho + (int64_t)i * g.n_z;
-      float* aa = acc + (int64_t)i * g.n_z;
-      for (int k = klo; k <= khi; ++k) {
-        const float m = kernel_at(r, (float)(k - klo), &bad) * rr[k];
-        if (m != 0.0f) unsafeAtomicAdd(&aa[k], m * invD);
-      }
-    }
-  }
-}
-
-// rho_l = acc_l / s_l (0 where s_l = 0), or acc_l without a sensitivity image; acc is cleared.
-__global__ void k_update(int64_t npix, const float* __restrict__ s, float* __restrict__ rho, float* __restrict__ acc) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
-    const float a = acc[p];
-    float v;
-    if (s) {
-      const float sv = s[p];
-      v = sv > 0.0f ? a / sv : 0.0f;
-    } else {
-      v = a;
-    }
-    rho[p] = v;
-    acc[p] = 0.0f;
-  }
+__global__ void k_fill_f64(double* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -299,15 +78,18 @@ __device__ inline void dlogp(const RowG& r, float jf, float* du, float* dw) {
   *dw = 0.5f / r.w - 0.5f * r.kl * ik - 0.5f * (r.bl - 2.0f * gk * r.gl + gk * gk * r.kl);
 }
 
-// Grid-stride over events, one wavefront per event.  Per block: double partial sums of
-// log D', (sum rho P dlogP/du)/D', (sum rho P dlogP/dw)/D' into red[3 * block + c].
+// Grid-stride over events, one wavefront per event, one lane per ellipse row.  Per block: double
+// partial sums of log D', (sum_i rho_i P'_i dlogP_i/du) / D' and the same for w, where
+// D' = sum_i rho_i P'_i and P' = P / (u sqrt(w) / 2 pi); written to red[3 * block + c].
+// With B given, sum_j P'_jl / D'_j (= sum_j P_jl / D_j) is added into B with double atomics.
 __global__ void __launch_bounds__(256) k_loglik_pass(Geo g, int64_t n, const EventRec* __restrict__ ev,
-                                                     const float* __restrict__ rho, float* __restrict__ B,
+                                                     const float* __restrict__ rho, double* __restrict__ B,
                                                      float* __restrict__ D_out, double* __restrict__ red,
                                                      unsigned long long* __restrict__ cnt) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wave = threadIdx.x / WAVE;
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+  const float norm = (float)(g.u * sqrt(g.w) / (2.0 * kPi));
   double s_log = 0.0, s_du = 0.0, s_dw = 0.0;
   unsigned long long nzero = 0, nbad_tot = 0;
   for (int64_t j = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wave; j < n; j += nwaves) {
@@ -318,16 +100,17 @@ __global__ void __launch_bounds__(256) k_loglik_pass(Geo g, int64_t n, const Eve
     }
     bool bad = false;
     float D = 0.0f, Du = 0.0f, Dw = 0.0f;
-    for (int base = e.r0; base <= e.r1; base += WAVE) {
-      const int i = base + lane;
+    for (int b0 = e.r0; b0 <= e.r1; b0 += WAVE) {
+      const int i = b0 + lane;
       int klo, khi;
       if (i <= e.r1 && row_interval(g, e, i, &klo, &khi)) {
-        const RowK r = row_constants(g, e, i, klo);
+        double kf, ks;
+        const RowK r = row_constants(g, e, i, klo, &kf, &ks);
         const RowG rg = row_gradient_constants(g, e, i, klo);
         const float* rr = rho + (int64_t)i * g.n_z;
         for (int k = klo; k <= khi; ++k) {
           const float jf = (float)(k - klo);
-          const float m = kernel_at(r, jf, &bad) * rr[k];
+          const float m = kernel_guarded(r, jf, &bad) * rr[k];
           float du, dw;
           dlogp(rg, jf, &du, &dw);
           D += m;
@@ -340,7 +123,7 @@ __global__ void __launch_bounds__(256) k_loglik_pass(Geo g, int64_t n, const Eve
     Du = wave_sum(Du);
     Dw = wave_sum(Dw);
     nbad_tot += wave_sum_u64(bad ? 1ull : 0ull);
-    if (D_out && lane == 0) D_out[j] = D * (float)(g.u * sqrt(g.w) / (2.0 * kPi));
+    if (D_out && lane == 0) D_out[j] = D * norm;
     if (!(D > 0.0f)) {
       nzero += 1;
       continue;
@@ -349,16 +132,18 @@ __global__ void __launch_bounds__(256) k_loglik_pass(Geo g, int64_t n, const Eve
     s_du += (double)Du / (double)D;
     s_dw += (double)Dw / (double)D;
     if (B) {
-      const float invD = 1.0f / D;
-      for (int base = e.r0; base <= e.r1; base += WAVE) {
-        const int i = base + lane;
+      const double invD = 1.0 / (double)D;
+      for (int b0 = e.r0; b0 <= e.r1; b0 += WAVE) {
+        const int i = b0 + lane;
         int klo, khi;
         if (i <= e.r1 && row_interval(g, e, i, &klo, &khi)) {
-          const RowK r = row_constants(g, e, i, klo);
-          float* bb = B + (int64_t)i * g.n_z;
+          double kf, ks;
+          const RowK r = row_constants(g, e, i, klo, &kf, &ks);
+          double* bb = B + (int64_t)i * g.n_z;
+          bool dummy = false;
           for (int k = klo; k <= khi; ++k) {
-            const float p = kernel_at(r, (float)(k - klo), &bad);
-            if (p != 0.0f) unsafeAtomicAdd(&bb[k], p * invD);
+            const float pv = kernel_guarded(r, (float)(k - klo), &dummy);
+            if (pv != 0.0f) unsafeAtomicAdd(&bb[k], (double)pv * invD);
           }
         }
       }
@@ -406,9 +191,9 @@ __global__ void __launch_bounds__(256) k_loglik_finish(Geo g, int nblocks, const
   }
   if (threadIdx.x == 0) {
     const double nvalid = (double)cnt[C_VALID];
-    // log(D / pi) with D = (u sqrt(w) / 2 pi) D'
-    const double lognorm = log(g.u * sqrt(g.w) / (2.0 * kPi) / kPi);
     const double nz = (double)cnt[C_ZERO_DEN];
+    // log(D / pi) = log D' + log(u sqrt(w) / (2 pi) / pi)
+    const double lognorm = log(g.u * sqrt(g.w) / (2.0 * kPi) / kPi);
     const double ll = sh[0][0] + (nvalid - nz) * lognorm - sh[3][0];
     out3[0] = nz > 0.0 ? -INFINITY : ll;
     out3[1] = sh[1][0] * (-2.0 * g.u / g.sigma_z);
@@ -417,9 +202,10 @@ __global__ void __launch_bounds__(256) k_loglik_finish(Geo g, int nblocks, const
 }
 
 // grad_rho = B - s (s = 1 when absent)
-__global__ void k_grad_rho(int64_t npix, const float* __restrict__ B, const float* __restrict__ s, float* __restrict__ out) {
+__global__ void k_grad_rho(int64_t npix, const double* __restrict__ B, const float* __restrict__ s,
+                           float* __restrict__ out) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x)
-    out[p] = B[p] - (s ? s[p] : 1.0f);
+    out[p] = (float)(B[p] - (s ? (double)s[p] : 1.0));
 }
 
 int grid_for(int64_t n, int block, int cap = 65536) {
@@ -437,33 +223,8 @@ hipError_t launch_sensitivity(const Geo& g, float* s, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_prepare(const Geo& g, const float* events, int64_t n, const Workspace& ws, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_prepare, dim3((unsigned)blocks), dim3(256), 0, st, g, events, n, ws.ev, ws.cnt);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_u64(unsigned long long* p, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill_u64, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_event_pass(const Geo& g, int64_t n, const Workspace& ws, const float* rho, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  const int64_t blocks = (n + 3) / 4;
-  hipLaunchKernelGGL(k_event_pass, dim3((unsigned)blocks), dim3(256), 0, st, g, n, ws.ev, rho, ws.acc, ws.cnt);
-  return hipGetLastError();
-}
-
-hipError_t launch_update(const Geo& g, const float* s, float* rho, const Workspace& ws, hipStream_t st) {
-  const int64_t npix = (int64_t)g.n_y * g.n_z;
-  hipLaunchKernelGGL(k_update, dim3(grid_for(npix, 256)), dim3(256), 0, st, npix, s, rho, ws.acc);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 
@@ -471,15 +232,11 @@ hipError_t launch_loglik(const Geo& g, int64_t n, const Workspace& ws, const flo
                          float* D_out, float* grad_rho, double* out3, hipStream_t st) {
   const int64_t npix = (int64_t)g.n_y * g.n_z;
   const int blocks = grid_for(n, 256 / WAVE, RED_SLOTS / 3);
-  if (grad_rho) {
-    hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(npix, 256)), dim3(256), 0, st, ws.acc, npix);
-  }
-  hipLaunchKernelGGL(k_loglik_pass, dim3(blocks), dim3(256), 0, st, g, n, ws.ev, rho, grad_rho ? ws.acc : nullptr,
+  if (grad_rho) hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(npix, 256)), dim3(256), 0, st, ws.B, npix);
+  hipLaunchKernelGGL(k_loglik_pass, dim3(blocks), dim3(256), 0, st, g, n, ws.ev, rho, grad_rho ? ws.B : nullptr,
                      D_out, ws.red, ws.cnt);
   hipLaunchKernelGGL(k_loglik_finish, dim3(1), dim3(256), 0, st, g, blocks, ws.red, rho, s, ws.cnt, out3);
-  if (grad_rho) {
-    hipLaunchKernelGGL(k_grad_rho, dim3(grid_for(npix, 256)), dim3(256), 0, st, npix, ws.acc, s, grad_rho);
-  }
+  if (grad_rho) hipLaunchKernelGGL(k_grad_rho, dim3(grid_for(npix, 256)), dim3(256), 0, st, npix, ws.B, s, grad_rho);
   return hipGetLastError();
 }
 

@@ -1,0 +1,204 @@
+// Per-event preparation and spatial binning (iteration-invariant, run once per event list).
+//
+//   k_prepare   direct reconstruction (Eq. 2), ellipse rows (App. B, Sec. 3), pixel count,
+//               validity and the bin of each event
+//   k_histogram events per bin
+//   k_scan      exclusive prefix sums of bin sizes and of workgroup items per bin
+//   k_scatter   records in bin order
+//   k_items     workgroup items: (bin, first event, count) with at most ev_per_wg events
+#include "jpet_device.h"
+
+namespace jpet {
+
+namespace {
+
+__device__ inline int clamp_index(double v, int lo, int hi) {
+  if (!(v >= (double)lo)) return lo;   // also catches NaN
+  if (v > (double)hi) return hi;
+  return (int)v;
+}
+
+__device__ uint32_t bin_of(const Geo& g, const Plan& p, const EventRec& e) {
+  int b = 0;
+  if (p.ntb > 1) b = clamp_index(floor((e.t - p.tmin) / p.dt), 0, p.ntb - 1);
+  const double tc = bin_slope(p, b);
+  const int ic = clamp_index(rint((e.y - g.y0) * g.ipix), 0, g.n_y - 1);
+  const int ty = ic / p.TY;
+  const int kmin = -max(shear_offset(g, tc, 0), shear_offset(g, tc, g.n_y - 1));
+  const double kz = (e.z - tc * e.y - g.z0) * g.ipix;
+  const int tz = clamp_index(floor((kz - (double)kmin) / (double)p.TZ), 0, p.ntz - 1);
+  return (uint32_t)(((int64_t)b * p.nty + ty) * p.ntz + tz);
+}
+
+__global__ void __launch_bounds__(256) k_prepare(Geo g, Plan p, const float* __restrict__ events, int64_t n,
+                                                 EventRec* __restrict__ ev, uint32_t* __restrict__ key,
+                                                 unsigned long long* __restrict__ cnt) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long valid = 0, pairs = 0;
+  if (j < n) {
+    const float zu = events[3 * j], zd = events[3 * j + 1], dl = events[3 * j + 2];
+    EventRec e;
+    e.r0 = 0;
+    e.r1 = -1;
+    e.npix = 0;
+    e.index = (int32_t)j;
+    e.t = e.c = e.y = e.z = 0.0;
+    uint32_t k = kNoBin;
+    const double hl = 0.5 * g.L;
+    if (isfinite(zu) && isfinite(zd) && isfinite(dl) && fabs((double)zu) <= hl && fabs((double)zd) <= hl) {
+      // Eq. 2, first forms
+      const double t = ((double)zu - (double)zd) / (2.0 * g.R);
+      const double c = sqrt(1.0 + t * t);
+      const double y = -0.5 * (double)dl / c;
+      const double z = 0.5 * ((double)zu + (double)zd + 2.0 * y * t);
+      e.t = t;
+      e.c = c;
+      e.y = y;
+      e.z = z;
+      // rows within the ellipse's half height 1.5 sigma_dl / c (App. B)
+      const double hy = 1.5 / (sqrt(g.wm) * c);
+      double a = ceil((y - hy - g.y0) * g.ipix);
+      double b = floor((y + hy - g.y0) * g.ipix);
+      if (a < 0.0) a = 0.0;
+      if (b > (double)(g.n_y - 1)) b = (double)(g.n_y - 1);
+      int first = 1 << 30, last = -1;
+      long long cntp = 0;
+      if (a <= b) {
+        for (int i = (int)a; i <= (int)b; ++i) {
+          int klo, khi;
+          if (row_interval(g, e, i, &klo, &khi)) {
+            if (first > i) first = i;
+            last = i;
+            cntp += khi - klo + 1;
+          }
+        }
+      }
+      if (cntp > 0) {
+        e.r0 = first;
+        e.r1 = last;
+        e.npix = (int)cntp;
+        valid = 1;
+        pairs = (unsigned long long)cntp;
+        if (p.tiled) k = bin_of(g, p, e);
+      }
+    }
+    ev[j] = e;
+    key[j] = k;
+  }
+  const unsigned long long v = wave_sum_u64(valid), pr = wave_sum_u64(pairs),
+                           in = wave_sum_u64(j < n ? 1ull : 0ull);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && in) {
+    atomicAdd(&cnt[C_VALID], v);
+    atomicAdd(&cnt[C_DROPPED], in - v);
+    atomicAdd(&cnt[C_PAIRS], pr);
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_histogram(const uint32_t* __restrict__ key, int64_t n,
+                                                   uint32_t* __restrict__ bin_count) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n && key[j] != kNoBin) atomicAdd(&bin_count[key[j]], 1u);
+}
+
+// Single workgroup: exclusive scans of the bin sizes and of the items per bin.
+__global__ void __launch_bounds__(1024) k_scan(int nbins, int ev_per_wg, const uint32_t* __restrict__ bin_count,
+                                               uint32_t* __restrict__ bin_start, uint32_t* __restrict__ item_start,
+                                               unsigned long long* __restrict__ cnt) {
+  __shared__ uint32_t s_ev[1024], s_it[1024];
+  const int T = blockDim.x;
+  const int chunk = (nbins + T - 1) / T;
+  const int lo = min(nbins, (int)threadIdx.x * chunk), hi = min(nbins, lo + chunk);
+  uint32_t se = 0, si = 0;
+  for (int b = lo; b < hi; ++b) {
+    const uint32_t c = bin_count[b];
+    se += c;
+    si += (c + ev_per_wg - 1) / ev_per_wg;
+  }
+  s_ev[threadIdx.x] = se;
+  s_it[threadIdx.x] = si;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {
+    uint32_t ae = 0, ai = 0;
+    if ((int)threadIdx.x >= off) {
+      ae = s_ev[threadIdx.x - off];
+      ai = s_it[threadIdx.x - off];
+    }
+    __syncthreads();
+    s_ev[threadIdx.x] += ae;
+    s_it[threadIdx.x] += ai;
+    __syncthreads();
+  }
+  uint32_t re = threadIdx.x ? s_ev[threadIdx.x - 1] : 0u, ri = threadIdx.x ? s_it[threadIdx.x - 1] : 0u;
+  for (int b = lo; b < hi; ++b) {
+    const uint32_t c = bin_count[b];
+    bin_start[b] = re;
+    item_start[b] = ri;
+    re += c;
+    ri += (c + ev_per_wg - 1) / ev_per_wg;
+  }
+  if (threadIdx.x == T - 1) {
+    bin_start[nbins] = s_ev[T - 1];
+    item_start[nbins] = s_it[T - 1];
+    cnt[C_ITEMS] = s_it[T - 1];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_scatter(const EventRec* __restrict__ ev, const uint32_t* __restrict__ key,
+                                                 int64_t n, const uint32_t* __restrict__ bin_start,
+                                                 uint32_t* __restrict__ bin_fill, EventRec* __restrict__ evs) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t k = key[j];
+  if (k == kNoBin) return;
+  const uint32_t pos = bin_start[k] + atomicAdd(&bin_fill[k], 1u);
+  evs[pos] = ev[j];
+}
+
+__global__ void __launch_bounds__(256) k_items(int nbins, int ev_per_wg, const uint32_t* __restrict__ bin_count,
+                                               const uint32_t* __restrict__ bin_start,
+                                               const uint32_t* __restrict__ item_start, BinItem* __restrict__ items) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  const uint32_t c = bin_count[b];
+  uint32_t q = item_start[b];
+  for (uint32_t s = 0; s < c; s += ev_per_wg, ++q) {
+    BinItem it;
+    it.bin = b;
+    it.start = (int32_t)(bin_start[b] + s);
+    it.count = (int32_t)min((uint32_t)ev_per_wg, c - s);
+    it.pad = 0;
+    items[q] = it;
+  }
+}
+
+int blocks_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+}  // namespace
+
+hipError_t launch_prepare(const Geo& g, const Plan& p, const float* events, int64_t n, const Workspace& ws,
+                          hipStream_t st) {
+  if (n > 0) {
+    hipLaunchKernelGGL(k_prepare, dim3(blocks_for(n, 256)), dim3(256), 0, st, g, p, events, n, ws.ev, ws.key, ws.cnt);
+  }
+  if (!p.tiled) return hipGetLastError();
+  const int64_t nb = p.nbins;
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(nb, 256)), dim3(256), 0, st, ws.bin_count, nb);
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(nb, 256)), dim3(256), 0, st, ws.bin_fill, nb);
+  if (n > 0) hipLaunchKernelGGL(k_histogram, dim3(blocks_for(n, 256)), dim3(256), 0, st, ws.key, n, ws.bin_count);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p.nbins, p.ev_per_wg, ws.bin_count, ws.bin_start,
+                     ws.item_start, ws.cnt);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, ws.ev, ws.key, n, ws.bin_start,
+                       ws.bin_fill, ws.evs);
+  }
+  hipLaunchKernelGGL(k_items, dim3(blocks_for(nb, 256)), dim3(256), 0, st, p.nbins, p.ev_per_wg, ws.bin_count,
+                     ws.bin_start, ws.item_start, ws.items);
+  return hipGetLastError();
+}
+
+}  // namespace jpet

@@ -46,7 +46,7 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("n_events", ctypes.c_int64), ("n_valid", ctypes.c_int64), ("n_dropped", ctypes.c_int64),
         ("n_zero_denominator", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
-        ("n_kappa_nonpositive", ctypes.c_int64),
+        ("n_kappa_nonpositive", ctypes.c_int64), ("n_unplaced_rows", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -74,6 +74,8 @@ def _lib():
         L.jpet_mlem_iterate.argtypes = [gp, vp, i64, vp, vp, i32, vp, sz, u32, sp, vp]
         L.jpet_loglik_grad.argtypes = [gp, ctypes.POINTER(ctypes.c_double), vp, i64, vp, vp, vp, vp, vp, vp, sz,
                                        u32, sp, vp]
+        L.jpet_profile_enable.argtypes = [ctypes.c_int]
+        L.jpet_profile_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
         _L = L
     return _L
 
@@ -107,6 +109,19 @@ def _need(t, name, dtype, shape=None):
         raise TypeError(f"{name} must be a contiguous {dtype} CUDA tensor")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def profile_enable(on: bool = True):
+    """Time every event-pass launch with HIP events on its stream (see jpet_profile_read)."""
+    _check(_lib().jpet_profile_enable(1 if on else 0), "jpet_profile_enable")
+
+
+def profile_read():
+    """(timed event-pass launches, their summed duration in ms) since the last read."""
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(_lib().jpet_profile_read(ctypes.byref(n), ctypes.byref(ms)), "jpet_profile_read")
+    return int(n.value), float(ms.value)
 
 
 def sensitivity(g: Geometry, device=None, stream=None) -> torch.Tensor:
