@@ -158,6 +158,28 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
                      const float* s, const float* rho, double* out3, float* grad_rho, float* D_out, void* ws,
                      size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream);
 
+/* Launch shape the library picks for jpet_mlem_iterate on this geometry and event count
+ * (diagnostics and tuning reports).  Host output. */
+typedef struct jpet_launch_info {
+  int32_t binned;        /* 1: binned LDS event pass; 0: generic one-wavefront-per-event pass */
+  int32_t tile_rows;     /* rows of a bin's tile core */
+  int32_t tile_cols;     /* sheared columns of a bin's tile core */
+  int32_t halo_rows;     /* rows added above and below the core */
+  int32_t halo_cols;     /* columns added on each side of the core */
+  int32_t t_bins;        /* bins along tan(theta~); 1 = no shear */
+  int32_t bins;          /* total bins */
+  int32_t waves;         /* wavefronts per workgroup */
+  int32_t row_cache;     /* pixels of a row held in registers between the two passes */
+  int32_t events_per_batch;
+  int32_t events_per_workgroup;
+  int32_t reserved;
+  double t_bin_width;    /* width of a tan(theta~) bin */
+  int64_t lds_bytes;     /* dynamic LDS per workgroup */
+  int64_t max_workgroups;/* launch grid of the event pass */
+} jpet_launch_info;
+
+int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_info* info);
+
 /* Kernel timing.  While enabled (enable != 0), every launch of the MLEM event pass made by
  * jpet_mlem_iterate is bracketed by a pair of HIP events recorded on the caller's stream (the
  * stream the kernel runs on).  jpet_profile_read waits for the recorded events, writes the

@@ -109,6 +109,9 @@ int do_prepare(const Geo& geo, const Plan& p, const float* events, int64_t n, co
 
 }  // namespace
 
+// LDS row-pitch alignment of the binned pass's column-major region
+static const int kBankAlign = 64;
+
 Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n) {
   Plan p;
   memset(&p, 0, sizeof(p));
@@ -126,53 +129,68 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n) {
       maxlen = c;
       break;
     }
-  const int waves = 16;
-  const int ev_per_batch = rows_max > 0 ? (64 * waves) / rows_max : 0;
-  const size_t lds_budget = 150 * 1024;
-  if (maxlen == 0 || ev_per_batch < 1) return p;  // generic pass
+  if (maxlen == 0 || rows_max > 64 * 16) return p;  // generic pass
   p.maxlen = maxlen;
-  p.waves = waves;
-  p.ev_per_batch = ev_per_batch < 64 ? ev_per_batch : 64;
   p.HY = (int)ceil(hy_px + 0.5) + 1;
-  // candidates: no shear, then t bins of decreasing width; tiles of decreasing size
+  // Candidates, best first: 8-wave workgroups whose region fits two per CU, then 16-wave
+  // workgroups with one region per CU; for each, no shear, then t bins of decreasing width;
+  // tiles of decreasing size.
+  const int wave_opts[] = {8, 16};
+  // dynamic LDS per workgroup: two 8-wave workgroups per CU, or one 16-wave workgroup (160 KB per
+  // CU, less the static batch buffers)
+  const size_t budget[] = {72 * 1024, 150 * 1024};
   const double dts[] = {0.0, 0.4, 0.2, 0.1, 0.05, 0.025};
   const int tiles[] = {32, 24, 16, 12, 8};
   bool found = false;
-  for (double dt : dts) {
-    // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
-    const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
-    const double hz = 3.0 * sqrt(0.5 * msz * msz + 0.25 * mdl * mdl * tau * tau);
-    const int HZ = (int)ceil(hz / pix + 1.0) + 1;
-    for (int T : tiles) {
-      const int RY = T + 2 * p.HY, W = T + 2 * HZ;
-      const size_t bytes = (size_t)RY * (size_t)W * 12u;
-      if (bytes > lds_budget) continue;
-      p.TY = T;
-      p.TZ = T;
-      p.HZ = HZ;
-      p.RY = RY;
-      p.W = W;
-      p.lds_bytes = bytes;
-      if (dt == 0.0) {
-        p.ntb = 1;
-        p.tmin = 0.0;
-        p.dt = 1.0;
-      } else {
-        p.ntb = (int)ceil(2.0 * tmax / dt);
-        if (p.ntb < 1) p.ntb = 1;
-        p.dt = dt;
-        p.tmin = -0.5 * dt * p.ntb;
+  for (int wi = 0; wi < 2 && !found; ++wi) {
+    const int waves = wave_opts[wi];
+    if (rows_max > 64 * waves) continue;
+    for (double dt : dts) {
+      // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
+      const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
+      const double hz = 3.0 * sqrt(0.5 * msz * msz + 0.25 * mdl * mdl * tau * tau);
+      const int HZ = (int)ceil(hz / pix + 1.0) + 1;
+      for (int T : tiles) {
+        // LDS: float image and 64-bit accumulators, column-major with the row pitch rounded up
+        // to the bank alignment; masked reads up to maxlen columns past the image must stay in
+        // the accumulator array (2 W >= maxlen)
+        const int RY = T + 2 * p.HY, W = T + 2 * HZ;
+        const int pitch = (RY + kBankAlign - 1) / kBankAlign * kBankAlign;
+        const size_t bytes = (size_t)pitch * (size_t)W * 12u;
+        if (bytes > budget[wi] || 2 * W < maxlen) continue;
+        p.pitch = pitch;
+        p.waves = waves;
+        p.TY = T;
+        p.TZ = T;
+        p.HZ = HZ;
+        p.RY = RY;
+        p.W = W;
+        p.lds_bytes = bytes;
+        if (dt == 0.0) {
+          p.ntb = 1;
+          p.tmin = 0.0;
+          p.dt = 1.0;
+        } else {
+          p.ntb = (int)ceil(2.0 * tmax / dt);
+          if (p.ntb < 1) p.ntb = 1;
+          p.dt = dt;
+          p.tmin = -0.5 * dt * p.ntb;
+        }
+        found = true;
+        break;
       }
-      found = true;
-      break;
+      if (found) break;
     }
-    if (found) break;
   }
   if (!found) {
     memset(&p, 0, sizeof(p));
     p.ntb = 1;
     p.dt = 1.0;
     return p;
+  }
+  {
+    const int epb = (64 * p.waves) / rows_max;
+    p.ev_per_batch = epb < 64 ? epb : 64;
   }
   p.nty = (g->n_y + p.TY - 1) / p.TY;
   // sheared column span: the widest over the t bins
@@ -291,6 +309,29 @@ int jpet_mlem_workspace_size(const jpet_geometry* g, int64_t n_events, size_t* b
   if (!bytes || n_events < 0) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n_events);
   *bytes = workspace_layout(p, n_events, npix_of(g), nullptr, nullptr);
+  return JPET_OK;
+}
+
+int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_info* info) {
+  int rc = check_geometry(g);
+  if (rc) return rc;
+  if (!info || n_events < 0) return JPET_EINVAL;
+  const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n_events);
+  memset(info, 0, sizeof(*info));
+  info->binned = p.tiled;
+  info->tile_rows = p.TY;
+  info->tile_cols = p.TZ;
+  info->halo_rows = p.HY;
+  info->halo_cols = p.HZ;
+  info->t_bins = p.ntb;
+  info->bins = p.nbins;
+  info->waves = p.waves;
+  info->row_cache = p.maxlen;
+  info->events_per_batch = p.ev_per_batch;
+  info->events_per_workgroup = p.ev_per_wg;
+  info->t_bin_width = p.ntb > 1 ? p.dt : 0.0;
+  info->lds_bytes = (int64_t)p.lds_bytes;
+  info->max_workgroups = p.max_items;
   return JPET_OK;
 }
 

@@ -45,6 +45,7 @@ struct Plan {
   int TY, TZ;           // tile core (rows, sheared columns)
   int HY, HZ;           // halo (rows, columns)
   int RY, W;            // region rows and width
+  int pitch;            // LDS row pitch of a region column (RY rounded up to the bank count)
   int ntb, nty, ntz;    // bins along t, y, z
   int nbins;
   double tmin, dt;      // t bin b spans [tmin + b dt, tmin + (b+1) dt); ntb == 1: no shear

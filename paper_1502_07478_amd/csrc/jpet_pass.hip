@@ -6,8 +6,7 @@
 //   pass 1  walks its row, evaluates the kernel at each pixel, multiplies by rho from LDS and
 //           keeps m = P rho in registers; the per-event denominators D = sum m are formed by a
 //           segmented wavefront reduction and a double-precision LDS add;
-//   pass 2  adds m / D in 2^-32 fixed point into the region's LDS accumulators (a 32-bit word
-//           whose carries go to a second word).
+//   pass 2  adds m / D in 2^-32 fixed point into the region's 64-bit LDS accumulators.
 // After the last batch the region's accumulators are added to the global 64-bit accumulator
 // image with one atomic per touched pixel.  Integer accumulation makes the new image exact
 // and independent of the order in which events are processed.
@@ -22,57 +21,69 @@ namespace {
 constexpr int kMaxBatch = 64;
 
 struct BatchShared {
-  EventRec ev[kMaxBatch];
+  EventRec ev[2][kMaxBatch];  // double buffer: the next batch is fetched while this one runs
   int cum[kMaxBatch + 1];
   double D[kMaxBatch];
   unsigned zero, bad, outside;
 };
 
+// The region is stored column-major with a row pitch that is a multiple of the LDS bank count:
+// the lanes of a wavefront hold consecutive rows of one event, so the pixel at column offset j
+// of every lane's row falls into a different bank whatever the slant of the ellipse.
+constexpr int kChunk = 4;  // pixels evaluated per branch-free step
+
 template <int MAXLEN, bool GUARD>
-__device__ __forceinline__ float pass1(const RowK& rk, const float* __restrict__ rho_s, int base, int len, int wl,
-                                       float (&m)[MAXLEN], bool* bad) {
+__device__ __forceinline__ float pass1(const RowK& rk, const float* __restrict__ rho_s, int base, int pitch, int len,
+                                       int wl, float (&m)[MAXLEN], bool* bad) {
   float D = 0.0f;
 #pragma unroll
-  for (int j = 0; j < MAXLEN; ++j) {
-    float v = 0.0f;
-    if (j < wl) {  // wavefront-uniform: skips the tail beyond the wavefront's longest row
-      if (j < len) {
-        const float p = GUARD ? kernel_guarded(rk, (float)j, bad) : kernel_fast(rk, (float)j);
-        v = p * rho_s[base + j];
+  for (int j0 = 0; j0 < MAXLEN; j0 += kChunk) {
+    if (j0 < wl) {  // wavefront-uniform
+      float r[kChunk];
+#pragma unroll
+      for (int jj = 0; jj < kChunk; ++jj) r[jj] = rho_s[base + (j0 + jj) * pitch];
+#pragma unroll
+      for (int jj = 0; jj < kChunk; ++jj) {
+        const int j = j0 + jj;
+        const float pv = GUARD ? kernel_guarded(rk, (float)j, bad) : kernel_fast(rk, (float)j);
+        const float v = j < len ? pv * r[jj] : 0.0f;
+        m[j] = v;
+        D += v;
       }
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < kChunk; ++jj) m[j0 + jj] = 0.0f;
     }
-    m[j] = v;
-    D += v;
   }
   return D;
 }
 
 template <int MAXLEN, bool PRESCALE>
-__device__ __forceinline__ void pass2(const float (&m)[MAXLEN], float sc, int base, int len, int wl,
-                                      unsigned* __restrict__ lo_s, unsigned* __restrict__ hi_s) {
+__device__ __forceinline__ void pass2(const float (&m)[MAXLEN], float sc, int base, int pitch, int len, int wl,
+                                      unsigned long long* __restrict__ acc_s) {
 #pragma unroll
   for (int j = 0; j < MAXLEN; ++j) {
-    if (j < wl && j < len && m[j] > 0.0f) {
+    if (j < wl && j < len) {
       const float x = PRESCALE ? m[j] * 18446744073709551616.0f : m[j];
-      const unsigned v = (unsigned)fmaf(x, sc, 0.5f);
-      const unsigned old = atomicAdd(&lo_s[base + j], v);
-      if (old + v < old) atomicAdd(&hi_s[base + j], 1u);
+      atomicAdd(&acc_s[base + j * pitch], (unsigned long long)(unsigned)fmaf(x, sc, 0.5f));
     }
   }
 }
 
-template <int MAXLEN>
-__global__ void __launch_bounds__(1024) k_event_pass_tiled(Geo g, Plan p, const EventRec* __restrict__ evs,
+template <int MAXLEN, int WAVES>
+__global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan p, const EventRec* __restrict__ evs,
                                                            const BinItem* __restrict__ items,
                                                            const float* __restrict__ rho,
                                                            unsigned long long* __restrict__ acc,
                                                            unsigned long long* __restrict__ cnt) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ BatchShared bs;
-  const int npx = p.RY * p.W;
+  const int pitch = p.pitch;  // rows of a column in LDS (a multiple of the bank count)
+  const int npx = pitch * p.W;
+  // the image first, then the accumulators: reads past the end of a row (masked lanes) land in
+  // the accumulator array, which is larger than MAXLEN columns of the image
   float* rho_s = reinterpret_cast<float*>(smem);
-  unsigned* lo_s = reinterpret_cast<unsigned*>(rho_s + npx);
-  unsigned* hi_s = lo_s + npx;
+  unsigned long long* acc_s = reinterpret_cast<unsigned long long*>(smem + (size_t)npx * sizeof(float));
 
   if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
   const BinItem it = items[blockIdx.x];
@@ -87,34 +98,39 @@ __global__ void __launch_bounds__(1024) k_event_pass_tiled(Geo g, Plan p, const 
   const int tid = threadIdx.x;
   const int lane = tid & (WAVE - 1);
 
-  // stage the region of the current image; clear the accumulators
+  // stage the region of the current image (column-major), clear the accumulators
   for (int q = tid; q < npx; q += blockDim.x) {
-    const int rl = q / p.W;
+    const int cl = q / pitch;
+    const int rl = q - cl * pitch;
     const int r = rbase + rl;
     float v = 0.0f;
-    if (r >= 0 && r < g.n_y) {
-      const int k = kbase + (q - rl * p.W) + shear_offset(g, tc, r);
+    if (rl < p.RY && r >= 0 && r < g.n_y) {
+      const int k = kbase + cl + shear_offset(g, tc, r);
       if (k >= 0 && k < g.n_z) v = rho[(int64_t)r * g.n_z + k];
     }
     rho_s[q] = v;
-    lo_s[q] = 0u;
-    hi_s[q] = 0u;
+    acc_s[q] = 0ull;
   }
   if (tid == 0) {
     bs.zero = 0u;
     bs.bad = 0u;
     bs.outside = 0u;
   }
+  if (tid < min(p.ev_per_batch, it.count)) bs.ev[0][tid] = evs[it.start + tid];
 
-  for (int e0 = 0; e0 < it.count; e0 += p.ev_per_batch) {
+  int buf = 0;
+  for (int e0 = 0; e0 < it.count; e0 += p.ev_per_batch, buf ^= 1) {
     const int nb = min(p.ev_per_batch, it.count - e0);
-    if (tid < nb) {
-      bs.ev[tid] = evs[it.start + e0 + tid];
-      bs.D[tid] = 0.0;
-    }
+    if (tid < nb) bs.D[tid] = 0.0;
     __syncthreads();
+    // fetch the next batch into the other buffer; it is read only after this batch's barriers
+    {
+      const int n1 = min(p.ev_per_batch, it.count - e0 - nb);
+      if (tid < n1) bs.ev[buf ^ 1][tid] = evs[it.start + e0 + nb + tid];
+    }
+    const EventRec* bev = bs.ev[buf];
     if (tid < WAVE) {  // rows per event, exclusive scan by the first wavefront
-      int nr = tid < nb ? bs.ev[tid].r1 - bs.ev[tid].r0 + 1 : 0;
+      int nr = tid < nb ? bev[tid].r1 - bev[tid].r0 + 1 : 0;
       int incl = nr;
 #pragma unroll
       for (int off = 1; off < WAVE; off <<= 1) {
@@ -138,7 +154,7 @@ __global__ void __launch_bounds__(1024) k_event_pass_tiled(Geo g, Plan p, const 
         if (bs.cum[mid] <= tid) lo = mid; else hi = mid - 1;
       }
       e = lo;
-      const EventRec ev = bs.ev[e];
+      const EventRec ev = bev[e];
       const int i = ev.r0 + (tid - bs.cum[e]);
       int klo, khi;
       if (row_interval(g, ev, i, &klo, &khi)) {
@@ -153,7 +169,7 @@ __global__ void __launch_bounds__(1024) k_event_pass_tiled(Geo g, Plan p, const 
           const double kl_end = kf + ks * (double)(n - 1);
           safe = kf > 1e-3 * fabs(kf) + 1e-30 && kl_end > 1e-3 * fabs(kf) + 1e-30;
           len = n;
-          base = rl * p.W + kl;
+          base = kl * pitch + rl;
         }
       }
     }
@@ -164,9 +180,9 @@ __global__ void __launch_bounds__(1024) k_event_pass_tiled(Geo g, Plan p, const 
     bool bad = false;
     float D;
     if (__any(!safe)) {
-      D = pass1<MAXLEN, true>(rk, rho_s, base, len, wl, m, &bad);
+      D = pass1<MAXLEN, true>(rk, rho_s, base, pitch, len, wl, m, &bad);
     } else {
-      D = pass1<MAXLEN, false>(rk, rho_s, base, len, wl, m, &bad);
+      D = pass1<MAXLEN, false>(rk, rho_s, base, pitch, len, wl, m, &bad);
     }
     if (bad) atomicAdd(&bs.bad, 1u);
 
@@ -190,10 +206,10 @@ __global__ void __launch_bounds__(1024) k_event_pass_tiled(Geo g, Plan p, const 
       // 2^32 / D overflows a float only for D < 1.3e-29; such wavefronts pre-scale m by 2^64
       if (__any(n2 > 0 && Dd < 1e-28)) {
         const float sc = (float)(4294967296.0 / (Dd * 18446744073709551616.0));
-        pass2<MAXLEN, true>(m, sc, base, n2, wl, lo_s, hi_s);
+        pass2<MAXLEN, true>(m, sc, base, pitch, n2, wl, acc_s);
       } else {
         const float sc = (float)(4294967296.0 / Dd);
-        pass2<MAXLEN, false>(m, sc, base, n2, wl, lo_s, hi_s);
+        pass2<MAXLEN, false>(m, sc, base, pitch, n2, wl, acc_s);
       }
     }
     __syncthreads();
@@ -201,13 +217,13 @@ __global__ void __launch_bounds__(1024) k_event_pass_tiled(Geo g, Plan p, const 
 
   // add the region's accumulators to the global image
   for (int q = tid; q < npx; q += blockDim.x) {
-    const unsigned lo = lo_s[q], hi = hi_s[q];
-    if ((lo | hi) == 0u) continue;
-    const int rl = q / p.W;
+    const unsigned long long a = acc_s[q];
+    if (a == 0ull) continue;
+    const int cl = q / pitch;
+    const int rl = q - cl * pitch;
     const int r = rbase + rl;
-    const int k = kbase + (q - rl * p.W) + shear_offset(g, tc, r);
-    if (r >= 0 && r < g.n_y && k >= 0 && k < g.n_z)
-      atomicAdd(&acc[(int64_t)r * g.n_z + k], ((unsigned long long)hi << 32) | (unsigned long long)lo);
+    const int k = kbase + cl + shear_offset(g, tc, r);
+    if (rl < p.RY && r >= 0 && r < g.n_y && k >= 0 && k < g.n_z) atomicAdd(&acc[(int64_t)r * g.n_z + k], a);
   }
   if (tid == 0) {
     if (bs.zero) atomicAdd(&cnt[C_ZERO_DEN], (unsigned long long)bs.zero);
@@ -280,9 +296,9 @@ __global__ void k_update(int64_t npix, const float* __restrict__ s, float* __res
   }
 }
 
-template <int MAXLEN>
+template <int MAXLEN, int WAVES>
 hipError_t launch_tiled(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, hipStream_t st) {
-  auto kern = k_event_pass_tiled<MAXLEN>;
+  auto kern = k_event_pass_tiled<MAXLEN, WAVES>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)p.max_items), dim3(64 * p.waves), p.lds_bytes, st, g, p, ws.evs, ws.items,
@@ -296,11 +312,16 @@ hipError_t launch_event_pass(const Geo& g, const Plan& p, int64_t n, const Works
                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (p.tiled) {
-    switch (p.maxlen) {
-      case 16: return launch_tiled<16>(g, p, ws, rho, st);
-      case 32: return launch_tiled<32>(g, p, ws, rho, st);
-      case 48: return launch_tiled<48>(g, p, ws, rho, st);
-      case 64: return launch_tiled<64>(g, p, ws, rho, st);
+    const int key = p.maxlen * 100 + p.waves;
+    switch (key) {
+      case 1608: return launch_tiled<16, 8>(g, p, ws, rho, st);
+      case 3208: return launch_tiled<32, 8>(g, p, ws, rho, st);
+      case 4808: return launch_tiled<48, 8>(g, p, ws, rho, st);
+      case 6408: return launch_tiled<64, 8>(g, p, ws, rho, st);
+      case 1616: return launch_tiled<16, 16>(g, p, ws, rho, st);
+      case 3216: return launch_tiled<32, 16>(g, p, ws, rho, st);
+      case 4816: return launch_tiled<48, 16>(g, p, ws, rho, st);
+      case 6416: return launch_tiled<64, 16>(g, p, ws, rho, st);
       default: return hipErrorInvalidValue;
     }
   }

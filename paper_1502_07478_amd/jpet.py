@@ -53,6 +53,16 @@ class Stats(ctypes.Structure):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
+class LaunchInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "binned", "tile_rows", "tile_cols", "halo_rows", "halo_cols", "t_bins", "bins", "waves", "row_cache",
+        "events_per_batch", "events_per_workgroup", "reserved")] + [
+        ("t_bin_width", ctypes.c_double), ("lds_bytes", ctypes.c_int64), ("max_workgroups", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
 _L = None
 
 
@@ -74,6 +84,7 @@ def _lib():
         L.jpet_mlem_iterate.argtypes = [gp, vp, i64, vp, vp, i32, vp, sz, u32, sp, vp]
         L.jpet_loglik_grad.argtypes = [gp, ctypes.POINTER(ctypes.c_double), vp, i64, vp, vp, vp, vp, vp, vp, sz,
                                        u32, sp, vp]
+        L.jpet_mlem_launch_info.argtypes = [gp, i64, ctypes.POINTER(LaunchInfo)]
         L.jpet_profile_enable.argtypes = [ctypes.c_int]
         L.jpet_profile_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
         _L = L
@@ -134,6 +145,13 @@ def workspace_size(g: Geometry, n_events: int) -> int:
     b = ctypes.c_size_t(0)
     _check(_lib().jpet_mlem_workspace_size(ctypes.byref(g), int(n_events), ctypes.byref(b)), "jpet_mlem_workspace_size")
     return int(b.value)
+
+
+def launch_info(g: Geometry, n_events: int) -> dict:
+    """The event pass's launch shape for this geometry and event count."""
+    info = LaunchInfo()
+    _check(_lib().jpet_mlem_launch_info(ctypes.byref(g), int(n_events), ctypes.byref(info)), "jpet_mlem_launch_info")
+    return info.as_dict()
 
 
 def workspace(g: Geometry, n_events: int, device=None) -> torch.Tensor:
