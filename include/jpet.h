@@ -141,6 +141,24 @@ int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, co
                       int32_t n_iter, void* ws, size_t ws_bytes, uint32_t flags, jpet_stats* stats,
                       void* stream);
 
+/* One event pass of jpet_mlem_iterate without the pixel update, for event lists processed in
+ * pieces (chunks of one acquisition that share the current image): for every valid event j with
+ * D_j = sum_{i in ellipse} P_ji rho_i > 0, adds round(2^32 rho_l P_jl / D_j) to acc_l for every
+ * pixel l of its ellipse (the accumulator of the Sec. 4 listing in 2^-32 fixed point).
+ *   events, n, rho, ws, ws_bytes, flags, stats: as for jpet_mlem_iterate (rho is only read)
+ *   acc:  device uint64 [n_y*n_z], added to; start it at 0 (e.g. after jpet_mlem_update or a
+ *         memset).  Integer sums make the result independent of the order of calls and events.
+ *         Up to 2^32 events' contributions fit before a pixel can overflow.
+ * stats counts this call's events. */
+int jpet_mlem_backproject(const jpet_geometry* g, const float* events, int64_t n, const float* rho, uint64_t* acc,
+                          void* ws, size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream);
+
+/* The pixel update of Eq. 3 (Eq. 5 with s NULL) from an accumulator filled by
+ * jpet_mlem_backproject:  rho_l = acc_l 2^-32 / s_l where s_l > 0, else 0 (s NULL: acc_l 2^-32);
+ * then acc_l = 0.
+ *   s: device float [n_y*n_z] or NULL; acc: device uint64 [n_y*n_z]; rho: device float, written. */
+int jpet_mlem_update(const jpet_geometry* g, const float* s, uint64_t* acc, float* rho, void* stream);
+
 /* Poisson list-mode log-likelihood of the image and its gradient (the objective whose EM step
  * is Eq. 3):
  *   l = sum_{valid j} log(D_j / pi) - sum_l s_l rho_l,     D_j = sum_{i in ellipse_j} P_ji rho_i
@@ -157,6 +175,33 @@ int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, co
 int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const float* events, int64_t n,
                      const float* s, const float* rho, double* out3, float* grad_rho, float* D_out, void* ws,
                      size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream);
+
+/* Batched reconstruction: many independent list-mode MLEM problems (each with its own geometry,
+ * resolution, event list, sensitivity and image) advanced together, one event-pass launch per
+ * iteration for the whole batch.  Each instance's result is that of jpet_mlem_iterate on it alone
+ * (to FP32 rounding of the denominators: events are grouped into workgroup batches the same way).
+ * Host struct; pointers as for jpet_mlem_iterate. */
+typedef struct jpet_instance {
+  jpet_geometry g;
+  const float* events; /* device float [n][3] */
+  int64_t n;           /* >= 0 */
+  const float* s;      /* device float [n_y*n_z] sensitivity, or NULL (Eq. 5) */
+  float* rho;          /* device float [n_y*n_z]: the image, updated in place */
+} jpet_instance;
+
+/* Workspace bytes for the batch (host output).  inst: host array of count instances,
+ * 0 <= count <= 65535. */
+int jpet_mlem_batched_workspace_size(const jpet_instance* inst, int32_t count, size_t* bytes);
+
+/* Per-event preparation of every instance (as jpet_mlem_prepare) into the batched workspace. */
+int jpet_mlem_batched_prepare(const jpet_instance* inst, int32_t count, void* ws, size_t ws_bytes, void* stream);
+
+/* n_iter MLEM iterations of every instance, in place on each rho.  flags: 0 or JPET_WS_PREPARED
+ * (the workspace holds jpet_mlem_batched_prepare's output for the same instance array: same
+ * geometries, event pointers and counts).  stats: host array of count entries, or NULL; entry k
+ * describes instance k (the call then synchronises).  Instances must not share rho arrays. */
+int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t n_iter, void* ws, size_t ws_bytes,
+                              uint32_t flags, jpet_stats* stats, void* stream);
 
 /* Launch shape the library picks for jpet_mlem_iterate on this geometry and event count
  * (diagnostics and tuning reports).  Host output. */
@@ -181,7 +226,8 @@ typedef struct jpet_launch_info {
 int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_info* info);
 
 /* Kernel timing.  While enabled (enable != 0), every launch of the MLEM event pass made by
- * jpet_mlem_iterate is bracketed by a pair of HIP events recorded on the caller's stream (the
+ * jpet_mlem_iterate, jpet_mlem_backproject and jpet_mlem_batched_iterate (one per iteration for
+ * the whole batch) is bracketed by a pair of HIP events recorded on the caller's stream (the
  * stream the kernel runs on).  jpet_profile_read waits for the recorded events, writes the
  * number of timed launches and their summed duration in milliseconds (host outputs, nullable)
  * and forgets them.  Disabling also forgets unread timings.  Process-wide, thread-safe; the

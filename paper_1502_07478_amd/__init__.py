@@ -5,5 +5,5 @@ include/jpet.h); ``paper_1502_07478_amd.jpet`` is its ctypes binding.
 """
 
 from . import jpet  # noqa: F401
-from .jpet import (Geometry, JpetError, Stats, geometry, loglik_grad, mlem, mlem_iterate, prepare,  # noqa: F401
-                   sensitivity, workspace, workspace_size)
+from .jpet import (BatchedMLEM, ChunkedMLEM, Geometry, JPetLogLik, JpetError, Stats, geometry, loglik, loglik_grad, mlem,  # noqa: F401
+                   mlem_iterate, prepare, sensitivity, workspace, workspace_size)

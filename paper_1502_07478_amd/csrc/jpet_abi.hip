@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -112,7 +113,7 @@ int do_prepare(const Geo& geo, const Plan& p, const float* events, int64_t n, co
 // LDS row-pitch alignment of the binned pass's column-major region
 static const int kBankAlign = 64;
 
-Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n) {
+Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int force_waves) {
   Plan p;
   memset(&p, 0, sizeof(p));
   p.ntb = 1;
@@ -144,7 +145,7 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n) {
   bool found = false;
   for (int wi = 0; wi < 2 && !found; ++wi) {
     const int waves = wave_opts[wi];
-    if (rows_max > 64 * waves) continue;
+    if (rows_max > 64 * waves || (force_waves && waves != force_waves)) continue;
     for (double dt : dts) {
       // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
       const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
@@ -157,7 +158,8 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n) {
         const int RY = T + 2 * p.HY, W = T + 2 * HZ;
         const int pitch = (RY + kBankAlign - 1) / kBankAlign * kBankAlign;
         const size_t bytes = (size_t)pitch * (size_t)W * 12u;
-        if (bytes > budget[wi] || 2 * W < maxlen) continue;
+        // thread words address columns with 8 bits and rows with 9 bits
+        if (bytes > budget[wi] || 2 * W < maxlen || W > 256 || RY > 512) continue;
         p.pitch = pitch;
         p.waves = waves;
         p.TY = T;
@@ -190,7 +192,9 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n) {
   }
   {
     const int epb = (64 * p.waves) / rows_max;
-    p.ev_per_batch = epb < 64 ? epb : 64;
+    p.ev_per_batch = epb < 32 ? epb : 32;
+    p.batch_bytes =
+        (int)((p.ev_per_batch * sizeof(EvConst) + 4u * 65u * (unsigned)p.waves + 255u) / 256u * 256u);
   }
   p.nty = (g->n_y + p.TY - 1) / p.TY;
   // sheared column span: the widest over the t bins
@@ -213,6 +217,8 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n) {
   const int64_t nonempty = n < p.nbins ? n : p.nbins;
   p.max_items = (n + p.ev_per_wg - 1) / p.ev_per_wg + nonempty;
   if (p.max_items < 1) p.max_items = 1;
+  p.max_batches = (n + p.ev_per_batch - 1) / p.ev_per_batch + nonempty;
+  if (p.max_batches < 1) p.max_batches = 1;
   p.tiled = 1;
   return p;
 }
@@ -237,19 +243,129 @@ size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Work
   w.key = (uint32_t*)take(sizeof(uint32_t) * nn);
   // binning (tiled pass only)
   w.evs = (EventRec*)take(p.tiled ? sizeof(EventRec) * nn : 0);
+  w.batches = (unsigned char*)take(p.tiled ? (size_t)p.batch_bytes * (size_t)p.max_batches : 0);
   w.bin_count = (uint32_t*)take(sizeof(uint32_t) * nb);
   w.bin_start = (uint32_t*)take(sizeof(uint32_t) * (nb + 1));
   w.bin_fill = (uint32_t*)take(sizeof(uint32_t) * nb);
   w.item_start = (uint32_t*)take(sizeof(uint32_t) * (nb + 1));
+  w.batch_start = (uint32_t*)take(sizeof(uint32_t) * (nb + 1));
   w.items = (BinItem*)take(p.tiled ? sizeof(BinItem) * (size_t)p.max_items : 0);
   w.bytes = off;
   if (out) *out = w;
   return off;
 }
 
+// Layout of a batched workspace: the instance table, then one ordinary workspace per instance.
+// Every binned instance runs with the same wavefront count and register-cache length (those of
+// the most demanding instance) so that one kernel serves the whole batch; the table is sorted by
+// estimated work per workgroup, heaviest first, so that the longest workgroups start earliest.
+struct BatchLayout {
+  int waves = 8;
+  int maxlen = 16;
+  size_t lds = 0;
+  std::vector<Plan> plan;      // per instance
+  std::vector<size_t> off;     // per instance: byte offset of its workspace
+  std::vector<int> order;      // table position -> instance
+  std::vector<int64_t> begin;  // per instance: first workgroup in the batched grid
+  int64_t grid = 0;
+  int64_t max_npix = 0;
+  size_t total = 0;
+};
+
+BatchLayout batch_layout(const jpet_instance* inst, int count) {
+  BatchLayout L;
+  L.plan.resize(count);
+  L.off.resize(count);
+  L.begin.resize(count);
+  bool need16 = false;
+  for (int k = 0; k < count; ++k) {
+    const Plan p = make_plan(&inst[k].g, inst[k].g.sigma_z, inst[k].g.sigma_dl, inst[k].n);
+    if (p.tiled && p.waves == 16) need16 = true;
+  }
+  L.waves = need16 ? 16 : 8;
+  std::vector<double> work(count, 0.0);
+  for (int k = 0; k < count; ++k) {
+    const jpet_geometry& g = inst[k].g;
+    Plan p = make_plan(&g, g.sigma_z, g.sigma_dl, inst[k].n, L.waves);
+    L.plan[k] = p;
+    if (p.tiled) {
+      if (p.maxlen > L.maxlen) L.maxlen = p.maxlen;
+      if (p.lds_bytes > L.lds) L.lds = p.lds_bytes;
+      // pixels of a typical ellipse (App. B half sizes at theta = 0) times events per workgroup
+      work[k] = (1.5 * g.sigma_dl / g.pixel) * (3.0 * g.sigma_z / sqrt(2.0) / g.pixel) * p.ev_per_wg;
+    }
+    const int64_t np = npix_of(&g);
+    if (np > L.max_npix) L.max_npix = np;
+  }
+  L.order.resize(count);
+  for (int k = 0; k < count; ++k) L.order[k] = k;
+  // tiled first by decreasing work (stable: ties keep the caller's order), generic instances last
+  std::stable_sort(L.order.begin(), L.order.end(), [&](int a, int b) {
+    if (L.plan[a].tiled != L.plan[b].tiled) return L.plan[a].tiled > L.plan[b].tiled;
+    return work[a] > work[b];
+  });
+  for (int t = 0; t < count; ++t) {
+    const int k = L.order[t];
+    L.begin[k] = L.grid;
+    if (L.plan[k].tiled) L.grid += L.plan[k].max_items;
+  }
+  size_t off = align_up(sizeof(BatchInst) * (size_t)count, 256);
+  for (int k = 0; k < count; ++k) {
+    L.off[k] = off;
+    off = align_up(off + workspace_layout(L.plan[k], inst[k].n, npix_of(&inst[k].g), nullptr, nullptr), 256);
+  }
+  L.total = off;
+  return L;
+}
+
+int check_instances(const jpet_instance* inst, int32_t count) {
+  if (count < 0 || count > 65535 || (count > 0 && !inst)) return JPET_EINVAL;
+  for (int k = 0; k < count; ++k) {
+    const int rc = check_geometry(&inst[k].g);
+    if (rc) return rc;
+    if (inst[k].n < 0 || (inst[k].n > 0 && !inst[k].events) || !inst[k].rho) return JPET_EINVAL;
+  }
+  return JPET_OK;
+}
+
 }  // namespace jpet
 
 using namespace jpet;
+
+// One event pass (per-iteration counters reset first), bracketed by timing events when profiling
+// is on.
+// Runs launch() bracketed by timing events when profiling is on.
+template <class F>
+static int timed(F launch, hipStream_t st) {
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool on = false;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    on = g_prof_on;
+  }
+  hipError_t e;
+  if (on) {
+    if ((e = hipEventCreate(&ev0)) != hipSuccess) return hip_fail(e);
+    if ((e = hipEventCreate(&ev1)) != hipSuccess) return hip_fail(e);
+    if ((e = hipEventRecord(ev0, st)) != hipSuccess) return hip_fail(e);
+  }
+  e = launch();
+  if (e != hipSuccess) return hip_fail(e);
+  if (on) {
+    if ((e = hipEventRecord(ev1, st)) != hipSuccess) return hip_fail(e);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_events.emplace_back(ev0, ev1);
+  }
+  return JPET_OK;
+}
+
+static int timed_event_pass(const Geo& geo, const Plan& p, int64_t n, const Workspace& w, const float* rho,
+                            hipStream_t st) {
+  // per-pass counters: zero-denominator events, non-positive kappa pairs, unplaced rows
+  hipError_t e = launch_fill_u64(w.cnt + C_ZERO_DEN, 2, st);
+  if (e != hipSuccess) return hip_fail(e);
+  return timed([&] { return launch_event_pass(geo, p, n, w, rho, st); }, st);
+}
 
 extern "C" {
 
@@ -367,31 +483,47 @@ int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, co
   hipError_t e = launch_fill_u64(w.acc, npix_of(g), st);
   if (e != hipSuccess) return hip_fail(e);
   for (int it = 0; it < n_iter; ++it) {
-    // per-iteration counters: zero-denominator events, non-positive kappa pairs, unplaced rows
-    e = launch_fill_u64(w.cnt + C_ZERO_DEN, 2, st);
-    if (e != hipSuccess) return hip_fail(e);
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    bool timed = false;
-    {
-      std::lock_guard<std::mutex> lk(g_prof_mu);
-      timed = g_prof_on;
-    }
-    if (timed) {
-      if ((e = hipEventCreate(&ev0)) != hipSuccess) return hip_fail(e);
-      if ((e = hipEventCreate(&ev1)) != hipSuccess) return hip_fail(e);
-      if ((e = hipEventRecord(ev0, st)) != hipSuccess) return hip_fail(e);
-    }
-    e = launch_event_pass(geo, p, n, w, rho, st);
-    if (e != hipSuccess) return hip_fail(e);
-    if (timed) {
-      if ((e = hipEventRecord(ev1, st)) != hipSuccess) return hip_fail(e);
-      std::lock_guard<std::mutex> lk(g_prof_mu);
-      g_prof_events.emplace_back(ev0, ev1);
-    }
+    rc = timed_event_pass(geo, p, n, w, rho, st);
+    if (rc) return rc;
     e = launch_update(geo, s, rho, w, st);
     if (e != hipSuccess) return hip_fail(e);
   }
   if (stats) return read_stats(w, n, stats, st);
+  return JPET_OK;
+}
+
+int jpet_mlem_backproject(const jpet_geometry* g, const float* events, int64_t n, const float* rho, uint64_t* acc,
+                          void* ws, size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream) {
+  int rc = check_geometry(g);
+  if (rc) return rc;
+  if (n < 0 || (n > 0 && !events) || !rho || !acc) return JPET_EINVAL;
+  if (flags & ~JPET_WS_PREPARED) return JPET_EINVAL;
+  const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
+  Workspace w;
+  rc = carve(p, g, n, ws, ws_bytes, &w);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Geo geo = make_geo(g, g->sigma_z, g->sigma_dl);
+  if (!(flags & JPET_WS_PREPARED)) {
+    rc = do_prepare(geo, p, events, n, w, st);
+    if (rc) return rc;
+  }
+  w.acc = reinterpret_cast<unsigned long long*>(acc);
+  rc = timed_event_pass(geo, p, n, w, rho, st);
+  if (rc) return rc;
+  if (stats) return read_stats(w, n, stats, st);
+  return JPET_OK;
+}
+
+int jpet_mlem_update(const jpet_geometry* g, const float* s, uint64_t* acc, float* rho, void* stream) {
+  int rc = check_geometry(g);
+  if (rc) return rc;
+  if (!acc || !rho) return JPET_EINVAL;
+  Workspace w;
+  memset(&w, 0, sizeof(w));
+  w.acc = reinterpret_cast<unsigned long long*>(acc);
+  const hipError_t e = launch_update(make_geo(g, g->sigma_z, g->sigma_dl), s, rho, w, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e);
   return JPET_OK;
 }
 
@@ -428,6 +560,106 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
     rc = read_stats(w, n, stats, st);
     if (rc) return rc;
     if (stats->n_zero_denominator > 0) return JPET_EDOMAIN;
+  }
+  return JPET_OK;
+}
+
+int jpet_mlem_batched_workspace_size(const jpet_instance* inst, int32_t count, size_t* bytes) {
+  if (!bytes) return JPET_EINVAL;
+  const int rc = check_instances(inst, count);
+  if (rc) return rc;
+  *bytes = batch_layout(inst, count).total;
+  return JPET_OK;
+}
+
+static int batched_carve(const jpet_instance* inst, int32_t count, void* ws, size_t ws_bytes, BatchLayout* L,
+                         std::vector<Workspace>* w) {
+  int rc = check_instances(inst, count);
+  if (rc) return rc;
+  *L = batch_layout(inst, count);
+  if (!ws || ((uintptr_t)ws & 255) != 0 || ws_bytes < L->total) return JPET_EWORKSPACE;
+  w->resize(count);
+  for (int k = 0; k < count; ++k) {
+    rc = carve(L->plan[k], &inst[k].g, inst[k].n, (char*)ws + L->off[k], ws_bytes - L->off[k], &(*w)[k]);
+    if (rc) return rc;
+  }
+  return JPET_OK;
+}
+
+int jpet_mlem_batched_prepare(const jpet_instance* inst, int32_t count, void* ws, size_t ws_bytes, void* stream) {
+  BatchLayout L;
+  std::vector<Workspace> w;
+  int rc = batched_carve(inst, count, ws, ws_bytes, &L, &w);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  for (int k = 0; k < count; ++k) {
+    const jpet_geometry& g = inst[k].g;
+    rc = do_prepare(make_geo(&g, g.sigma_z, g.sigma_dl), L.plan[k], inst[k].events, inst[k].n, w[k], st);
+    if (rc) return rc;
+  }
+  return JPET_OK;
+}
+
+int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t n_iter, void* ws, size_t ws_bytes,
+                              uint32_t flags, jpet_stats* stats, void* stream) {
+  if (n_iter < 0 || (flags & ~JPET_WS_PREPARED)) return JPET_EINVAL;
+  BatchLayout L;
+  std::vector<Workspace> w;
+  int rc = batched_carve(inst, count, ws, ws_bytes, &L, &w);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<Geo> geo(count);
+  for (int k = 0; k < count; ++k) geo[k] = make_geo(&inst[k].g, inst[k].g.sigma_z, inst[k].g.sigma_dl);
+  if (!(flags & JPET_WS_PREPARED)) {
+    for (int k = 0; k < count; ++k) {
+      rc = do_prepare(geo[k], L.plan[k], inst[k].events, inst[k].n, w[k], st);
+      if (rc) return rc;
+    }
+  }
+  // the instance table (in table order), written by small launches so that it stays stream-ordered
+  BatchInst* table = reinterpret_cast<BatchInst*>(ws);
+  hipError_t e;
+  for (int t0 = 0; t0 < count; t0 += kInstPerWrite) {
+    InstWrite iw;
+    memset(&iw, 0, sizeof(iw));
+    iw.first = t0;
+    iw.count = count - t0 < kInstPerWrite ? count - t0 : kInstPerWrite;
+    for (int j = 0; j < iw.count; ++j) {
+      const int k = L.order[t0 + j];
+      BatchInst& b = iw.v[j];
+      b.g = geo[k];
+      b.p = L.plan[k];
+      b.tiled = L.plan[k].tiled;
+      b.index = k;
+      b.item_begin = L.begin[k];
+      b.n = inst[k].n;
+      b.blocks = w[k].batches;
+      b.items = w[k].items;
+      b.rho = inst[k].rho;
+      b.s = inst[k].s;
+      b.acc = w[k].acc;
+      b.cnt = w[k].cnt;
+    }
+    if ((e = launch_write_insts(iw, table, st)) != hipSuccess) return hip_fail(e);
+  }
+  for (int k = 0; k < count; ++k)
+    if ((e = launch_fill_u64(w[k].acc, npix_of(&inst[k].g), st)) != hipSuccess) return hip_fail(e);
+  for (int it = 0; it < n_iter; ++it) {
+    if ((e = launch_batched_reset(table, count, st)) != hipSuccess) return hip_fail(e);
+    rc = timed([&] { return launch_event_pass_batched(table, count, L.maxlen, L.waves, L.lds, L.grid, st); }, st);
+    if (rc) return rc;
+    for (int k = 0; k < count; ++k) {
+      if (L.plan[k].tiled) continue;
+      if ((e = launch_event_pass(geo[k], L.plan[k], inst[k].n, w[k], inst[k].rho, st)) != hipSuccess)
+        return hip_fail(e);
+    }
+    if ((e = launch_update_batched(table, count, L.max_npix, st)) != hipSuccess) return hip_fail(e);
+  }
+  if (stats) {
+    for (int k = 0; k < count; ++k) {
+      rc = read_stats(w[k], inst[k].n, &stats[k], st);
+      if (rc) return rc;
+    }
   }
   return JPET_OK;
 }

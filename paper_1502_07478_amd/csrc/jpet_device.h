@@ -34,6 +34,25 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
   return v;
 }
 
+// Cross-lane data movement within a wavefront through DPP (VALU, no LDS round trip).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+// Sum over the 64 lanes of a wavefront (all lanes active), returned to every lane: quad
+// permutations, half-row and row mirrors give each 16-lane row its sum; two row broadcasts
+// accumulate the rows into lane 63, which is read back as a wavefront-uniform value.
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dpp_f<0xB1>(v);       // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E>(v);       // quad_perm [2,3,0,1]
+  v += dpp_f<0x141>(v);      // row_half_mirror
+  v += dpp_f<0x140>(v);      // row_mirror
+  v += dpp_f<0x142, 0xa>(v); // row_bcast:15 into rows 1 and 3
+  v += dpp_f<0x143, 0xc>(v); // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __device__ inline int wave_max_i(int v) {
 #pragma unroll
   for (int off = WAVE / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, WAVE));

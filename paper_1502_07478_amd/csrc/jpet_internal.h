@@ -32,6 +32,26 @@ struct EventRec {
   int32_t index; // position of the event in the caller's array
 };
 
+// Per-event constants of the binned event pass (64 bytes), written at prepare time.  With Y the
+// row's y, dy = Y - y~ and b1 = z - z~ - dy tan (Eq. 8-11, gamma = 0):
+//   kappa = aC^-1a + 2 oC^-1b = A1 (R^2 + Y^2) + A2 Y^2 + A3 Y dy + KB Y b1
+//   gamma = bC^-1a           = G1 Y dy + GB Y b1
+//   S q   = S bC^-1b         = S 2u b1^2 + Q3s dy^2            (S = log2(e) / 2)
+struct EvConst {
+  double y, z;          // y~, z~
+  float t;              // tan(theta~)
+  float A1, A2, A3, KB; // 2u c^4, w fa^2 c^2 t^2, 4 w c^2 (1 + 2t^2), -4 u t c^2
+  float G1, GB, Q3s;    // 2 fa w c^2 t, -2 u c^2, S 4 w c^2
+  int32_t pad[4];
+};
+
+static_assert(sizeof(EvConst) == 64, "EvConst is copied to LDS in 16-byte units");
+
+// Thread word of the binned pass: the pixel row a thread owns in a batch, relative to its bin's
+// region: bits 0-7 first column (sheared, region-local), 8-16 row (region-local), 17-23 pixel
+// count (0: idle thread), 24-28 event within the batch.
+constexpr uint32_t kWordCol = 0, kWordRow = 8, kWordLen = 17, kWordEv = 24;
+
 // Spatial binning of events and launch shape of the tiled event pass.
 //
 // Events are binned by the pixel row of y~ (tiles of TY rows), by a column in a frame sheared
@@ -46,6 +66,8 @@ struct Plan {
   int HY, HZ;           // halo (rows, columns)
   int RY, W;            // region rows and width
   int pitch;            // LDS row pitch of a region column (RY rounded up to the bank count)
+  int batch_bytes;      // stride of a batch block: ev_per_batch EvConst, 64 * waves thread words, then
+                        // the longest row of each wavefront (waves ints)
   int ntb, nty, ntz;    // bins along t, y, z
   int nbins;
   double tmin, dt;      // t bin b spans [tmin + b dt, tmin + (b+1) dt); ntb == 1: no shear
@@ -54,6 +76,7 @@ struct Plan {
   int ev_per_batch;     // events whose rows are processed together (rows <= 64 * waves)
   int ev_per_wg;        // events per workgroup item (a multiple of ev_per_batch)
   int64_t max_items;    // upper bound of workgroup items (the launch grid)
+  int64_t max_batches;  // upper bound of batch blocks
   size_t lds_bytes;     // dynamic LDS of the tiled pass
 };
 
@@ -73,18 +96,20 @@ struct BinItem {
   int32_t bin;
   int32_t start;  // first event in the sorted record array
   int32_t count;
-  int32_t pad;
+  int32_t batch;  // first batch block of the item
 };
 
 // Workspace carve-up.
 struct Workspace {
   EventRec* ev;               // [n] records in input order
   EventRec* evs;              // [n] records sorted by bin
+  unsigned char* batches;     // [max_batches * batch_bytes] batch blocks of the binned pass
   uint32_t* key;              // [n] bin of each event (0xffffffff: dropped)
   uint32_t* bin_count;        // [nbins]
   uint32_t* bin_start;        // [nbins + 1]
   uint32_t* bin_fill;         // [nbins]
   uint32_t* item_start;       // [nbins + 1]
+  uint32_t* batch_start;      // [nbins + 1] first batch block of each bin
   BinItem* items;             // [max_items]
   unsigned long long* acc;    // [npix] back-projection accumulator, units of 2^-32
   double* B;                  // [npix] sum_j P_jl / D_j (log-likelihood gradient)
@@ -93,10 +118,35 @@ struct Workspace {
   size_t bytes;
 };
 
+// One reconstruction of a batch, as the batched kernels read it from the workspace's instance
+// table (sorted by item_begin).
+struct BatchInst {
+  Geo g;
+  Plan p;
+  int32_t tiled;              // 1: binned pass inside the batched launch; 0: generic pass, launched apart
+  int32_t index;              // position in the caller's instance array
+  int64_t item_begin;         // first workgroup of this instance in the batched grid
+  int64_t n;                  // events
+  const unsigned char* blocks;
+  const BinItem* items;
+  float* rho;                 // current image: read by the event pass, rewritten by the update
+  const float* s;             // sensitivity or null
+  unsigned long long* acc;
+  unsigned long long* cnt;
+};
+
+constexpr int kInstPerWrite = 6;  // instances written per table-writing launch (by-value kernel argument)
+struct InstWrite {
+  BatchInst v[kInstPerWrite];
+  int first, count;
+};
+static_assert(sizeof(InstWrite) <= 4096, "InstWrite is passed by value as a kernel argument");
+
 constexpr int RED_SLOTS = 4096;
 constexpr uint32_t kNoBin = 0xffffffffu;
 
-Plan make_plan(const jpet_geometry* g, double mask_sz, double mask_sdl, int64_t n);
+// force_waves: 0 = choose; 8 or 16 = only plans with that many wavefronts per workgroup
+Plan make_plan(const jpet_geometry* g, double mask_sz, double mask_sdl, int64_t n, int force_waves = 0);
 size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Workspace* out);
 
 // Kernel launchers (return the hipError_t of the launch).
@@ -107,6 +157,12 @@ hipError_t launch_prepare(const Geo& g, const Plan& p, const float* events, int6
 hipError_t launch_event_pass(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
                              hipStream_t st);
 hipError_t launch_update(const Geo& g, const float* s, float* rho, const Workspace& ws, hipStream_t st);
+// batched: table of count instances in device memory; grid = total workgroups of the tiled ones
+hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t st);
+hipError_t launch_batched_reset(const BatchInst* table, int count, hipStream_t st);
+hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxlen, int waves, size_t lds_bytes,
+                                     int64_t grid, hipStream_t st);
+hipError_t launch_update_batched(const BatchInst* table, int count, int64_t max_npix, hipStream_t st);
 hipError_t launch_loglik(const Geo& g, int64_t n, const Workspace& ws, const float* rho, const float* s,
                          float* D_out, float* grad_rho, double* out3, hipStream_t st);
 

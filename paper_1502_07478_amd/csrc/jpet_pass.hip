@@ -18,23 +18,28 @@ namespace jpet {
 
 namespace {
 
-constexpr int kMaxBatch = 64;
+constexpr int kMaxBatch = 32;  // events per batch (the plan keeps ev_per_batch <= 32)
+constexpr int kMaxRows = 512;  // region rows (the plan keeps RY <= 512)
+constexpr int kChunk = 4;      // pixels evaluated per branch-free step
 
-struct BatchShared {
-  EventRec ev[2][kMaxBatch];  // double buffer: the next batch is fetched while this one runs
-  int cum[kMaxBatch + 1];
-  double D[kMaxBatch];
-  unsigned zero, bad, outside;
+struct PassShared {
+  EvConst ev[2][kMaxBatch];  // double buffer: the next batch is copied in while this one runs
+  double D[2][kMaxBatch];
+  int off[kMaxRows];         // sheared column shift of each region row
+  unsigned zero, bad;
 };
 
-// The region is stored column-major with a row pitch that is a multiple of the LDS bank count:
-// the lanes of a wavefront hold consecutive rows of one event, so the pixel at column offset j
-// of every lane's row falls into a different bank whatever the slant of the ellipse.
-constexpr int kChunk = 4;  // pixels evaluated per branch-free step
+// Single-precision kernel constants along one pixel row (Eq. 7-11, gamma = 0); j is the pixel's
+// offset in the row:
+//   kappa_j = kap0 + j dkap,  sqrt(S) gamma_j = gs0 + j dgs,  S q_j = (qa j + qb) j + qc
+// and P / (u sqrt(w) / 2 pi) = kappa^-1/2 exp2(S gamma^2 / kappa - S q), S = log2(e) / 2.
+struct RowF {
+  float kap0, dkap, gs0, dgs, qb, qc;
+};
 
 template <int MAXLEN, bool GUARD>
-__device__ __forceinline__ float pass1(const RowK& rk, const float* __restrict__ rho_s, int base, int pitch, int len,
-                                       int wl, float (&m)[MAXLEN], bool* bad) {
+__device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __restrict__ rho_s, int base, int pitch,
+                                       int len, int wl, float (&m)[MAXLEN], bool* bad) {
   float D = 0.0f;
 #pragma unroll
   for (int j0 = 0; j0 < MAXLEN; j0 += kChunk) {
@@ -45,8 +50,20 @@ __device__ __forceinline__ float pass1(const RowK& rk, const float* __restrict__
 #pragma unroll
       for (int jj = 0; jj < kChunk; ++jj) {
         const int j = j0 + jj;
-        const float pv = GUARD ? kernel_guarded(rk, (float)j, bad) : kernel_fast(rk, (float)j);
-        const float v = j < len ? pv * r[jj] : 0.0f;
+        const float jf = (float)j;
+        float kap = fmaf(jf, rk.dkap, rk.kap0);
+        bool keep = j < len;
+        if (GUARD && !(kap > 0.0f)) {
+          if (keep) *bad = true;
+          keep = false;
+          kap = 1.0f;
+        }
+        const float gs = fmaf(jf, rk.dgs, rk.gs0);
+        const float rq = __builtin_amdgcn_rsqf(kap);
+        const float sq = fmaf(fmaf(qa, jf, rk.qb), jf, rk.qc);
+        const float tg = gs * rq;
+        const float pv = rq * __builtin_amdgcn_exp2f(fmaf(tg, tg, -sq));
+        const float v = keep ? pv * r[jj] : 0.0f;
         m[j] = v;
         D += v;
       }
@@ -70,23 +87,37 @@ __device__ __forceinline__ void pass2(const float (&m)[MAXLEN], float sc, int ba
   }
 }
 
+// Copies a batch's per-event constants into LDS with direct global-to-LDS loads issued by the
+// first wavefront (16 bytes per lane, 1 KB per instruction); completion is awaited before the
+// next workgroup barrier.
+__device__ __forceinline__ void copy_consts(const unsigned char* __restrict__ src, EvConst* dst, int bytes, int tid) {
+  if (tid < WAVE) {
+    for (int off = 0; off < bytes; off += WAVE * 16) {
+      if (off + tid * 16 < bytes)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint4*>(src + off + tid * 16),
+                                         reinterpret_cast<unsigned char*>(dst) + off, 16, 0, 0);
+    }
+  }
+}
+
+// The region is stored column-major with a row pitch that is a multiple of the LDS bank count.
+// Each thread owns the pixel row its thread word names (built at prepare time so that a
+// wavefront holds rows of nearly equal length, consecutive within each half-wavefront), so the
+// pixel at column offset j of every lane's row falls into a different bank whatever the slant of
+// the ellipse.
 template <int MAXLEN, int WAVES>
-__global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan p, const EventRec* __restrict__ evs,
-                                                           const BinItem* __restrict__ items,
-                                                           const float* __restrict__ rho,
-                                                           unsigned long long* __restrict__ acc,
-                                                           unsigned long long* __restrict__ cnt) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ BatchShared bs;
-  const int pitch = p.pitch;  // rows of a column in LDS (a multiple of the bank count)
+__device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, const unsigned char* __restrict__ blocks,
+                                                const BinItem it, const float* __restrict__ rho,
+                                                unsigned long long* __restrict__ acc,
+                                                unsigned long long* __restrict__ cnt, unsigned char* smem,
+                                                PassShared& ps) {
+  const int pitch = p.pitch;  // rows of a column in LDS
   const int npx = pitch * p.W;
   // the image first, then the accumulators: reads past the end of a row (masked lanes) land in
   // the accumulator array, which is larger than MAXLEN columns of the image
   float* rho_s = reinterpret_cast<float*>(smem);
   unsigned long long* acc_s = reinterpret_cast<unsigned long long*>(smem + (size_t)npx * sizeof(float));
 
-  if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
-  const BinItem it = items[blockIdx.x];
   const int tz = it.bin % p.ntz;
   const int rest = it.bin / p.ntz;
   const int ty = rest % p.nty;
@@ -97,8 +128,31 @@ __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan 
   const int kbase = kmin + tz * p.TZ - p.HZ;
   const int tid = threadIdx.x;
   const int lane = tid & (WAVE - 1);
+  const float pixf = (float)g.pixel;
+  const float S2u = (float)(kHalfLog2e * 2.0 * g.u);
+  const float qa = S2u * pixf * pixf;
+  const float R2 = (float)(g.R * g.R);
+  const float rs = 0.84932180028801904272f;  // sqrt(log2(e) / 2)
+  const int nbatch = (it.count + p.ev_per_batch - 1) / p.ev_per_batch;
+  const int cbytes = p.ev_per_batch * (int)sizeof(EvConst);
+  const unsigned char* blk0 = blocks + (size_t)it.batch * (size_t)p.batch_bytes;
 
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wl_off = cbytes + 4 * 64 * WAVES + 4 * wave;  // this wavefront's longest row
+  // first batch: constants to LDS, this thread's word and its wavefront's longest row
+  copy_consts(blk0, ps.ev[0], cbytes, tid);
+  uint32_t word = reinterpret_cast<const uint32_t*>(blk0 + cbytes)[tid];
+  int wl = *reinterpret_cast<const int*>(blk0 + wl_off);
+  if (tid < kMaxBatch) {
+    ps.D[0][tid] = 0.0;
+    ps.D[1][tid] = 0.0;
+  }
+  if (tid == 0) {
+    ps.zero = 0u;
+    ps.bad = 0u;
+  }
   // stage the region of the current image (column-major), clear the accumulators
+  for (int r = tid; r < p.RY; r += blockDim.x) ps.off[r] = shear_offset(g, tc, rbase + r);
   for (int q = tid; q < npx; q += blockDim.x) {
     const int cl = q / pitch;
     const int rl = q - cl * pitch;
@@ -111,97 +165,77 @@ __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan 
     rho_s[q] = v;
     acc_s[q] = 0ull;
   }
-  if (tid == 0) {
-    bs.zero = 0u;
-    bs.bad = 0u;
-    bs.outside = 0u;
-  }
-  if (tid < min(p.ev_per_batch, it.count)) bs.ev[0][tid] = evs[it.start + tid];
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 
-  int buf = 0;
-  for (int e0 = 0; e0 < it.count; e0 += p.ev_per_batch, buf ^= 1) {
-    const int nb = min(p.ev_per_batch, it.count - e0);
-    if (tid < nb) bs.D[tid] = 0.0;
-    __syncthreads();
-    // fetch the next batch into the other buffer; it is read only after this batch's barriers
-    {
-      const int n1 = min(p.ev_per_batch, it.count - e0 - nb);
-      if (tid < n1) bs.ev[buf ^ 1][tid] = evs[it.start + e0 + nb + tid];
+  for (int bi = 0, buf = 0; bi < nbatch; ++bi, buf ^= 1) {
+    const int nb = min(p.ev_per_batch, it.count - bi * p.ev_per_batch);
+    // prefetch the next batch: constants into the other LDS buffer, this thread's next word
+    uint32_t next = 0u;
+    int wl_next = 0;
+    if (bi + 1 < nbatch) {
+      const unsigned char* blk = blk0 + (size_t)(bi + 1) * (size_t)p.batch_bytes;
+      copy_consts(blk, ps.ev[buf ^ 1], cbytes, tid);
+      next = reinterpret_cast<const uint32_t*>(blk + cbytes)[tid];
+      wl_next = *reinterpret_cast<const int*>(blk + wl_off);
     }
-    const EventRec* bev = bs.ev[buf];
-    if (tid < WAVE) {  // rows per event, exclusive scan by the first wavefront
-      int nr = tid < nb ? bev[tid].r1 - bev[tid].r0 + 1 : 0;
-      int incl = nr;
-#pragma unroll
-      for (int off = 1; off < WAVE; off <<= 1) {
-        const int o = __shfl_up(incl, off, WAVE);
-        if (lane >= off) incl += o;
-      }
-      if (tid < nb) bs.cum[tid] = incl - nr;
-      if (tid == nb - 1) bs.cum[nb] = incl;
-    }
-    __syncthreads();
 
-    // this thread's row: event e (largest with cum[e] <= tid), row i
-    const int total = bs.cum[nb];
-    int e = 0, len = 0, base = 0;
+    // this thread's row
+    const int len = (int)((word >> kWordLen) & 127u);
+    const int e = (int)((word >> kWordEv) & 31u);
+    int base = 0;
     bool safe = true;
-    RowK rk;
-    if (tid < total) {
-      int lo = 0, hi = nb - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (bs.cum[mid] <= tid) lo = mid; else hi = mid - 1;
-      }
-      e = lo;
-      const EventRec ev = bev[e];
-      const int i = ev.r0 + (tid - bs.cum[e]);
-      int klo, khi;
-      if (row_interval(g, ev, i, &klo, &khi)) {
-        const int rl = i - rbase;
-        const int kl = klo - shear_offset(g, tc, i) - kbase;
-        const int n = khi - klo + 1;
-        if (rl < 0 || rl >= p.RY || kl < 0 || kl + n > p.W || n > MAXLEN) {
-          atomicAdd(&bs.outside, 1u);
-        } else {
-          double kf, ks;
-          rk = row_constants(g, ev, i, klo, &kf, &ks);
-          const double kl_end = kf + ks * (double)(n - 1);
-          safe = kf > 1e-3 * fabs(kf) + 1e-30 && kl_end > 1e-3 * fabs(kf) + 1e-30;
-          len = n;
-          base = kl * pitch + rl;
-        }
-      }
+    RowF rk = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (len > 0) {
+      const int kl = (int)((word >> kWordCol) & 255u);
+      const int rl = (int)((word >> kWordRow) & 511u);
+      const EvConst& c = ps.ev[buf][e];
+      const int i = rbase + rl;
+      const int klo = kl + kbase + ps.off[rl];
+      const double Yd = g.y0 + (double)i * g.pixel;
+      const double dyd = Yd - c.y;
+      const double b10d = g.z0 + (double)klo * g.pixel - (c.z + (double)c.t * dyd);
+      const float Y = (float)Yd, dy = (float)dyd, b10 = (float)b10d;
+      const float kr = fmaf(c.A1, R2 + Y * Y, Y * fmaf(c.A2, Y, c.A3 * dy));
+      const float kb = c.KB * Y;
+      const float gb = c.GB * Y;
+      rk.kap0 = fmaf(kb, b10, kr);
+      rk.dkap = kb * pixf;
+      rk.gs0 = rs * fmaf(gb, b10, c.G1 * Y * dy);
+      rk.dgs = rs * gb * pixf;
+      rk.qb = 2.0f * S2u * b10 * pixf;
+      rk.qc = fmaf(S2u * b10, b10, c.Q3s * dy * dy);
+      const float kend = fmaf((float)(len - 1), rk.dkap, rk.kap0);
+      safe = rk.kap0 > 1e-3f * fabsf(rk.kap0) && kend > 1e-3f * fabsf(rk.kap0);
+      base = kl * pitch + rl;
     }
 
     // pass 1: m = P rho along the row, D partial sums
     float m[MAXLEN];
-    const int wl = wave_max_i(len);
     bool bad = false;
     float D;
     if (__any(!safe)) {
-      D = pass1<MAXLEN, true>(rk, rho_s, base, pitch, len, wl, m, &bad);
+      D = pass1<MAXLEN, true>(rk, qa, rho_s, base, pitch, len, wl, m, &bad);
     } else {
-      D = pass1<MAXLEN, false>(rk, rho_s, base, pitch, len, wl, m, &bad);
+      D = pass1<MAXLEN, false>(rk, qa, rho_s, base, pitch, len, wl, m, &bad);
     }
-    if (bad) atomicAdd(&bs.bad, 1u);
+    if (bad) atomicAdd(&ps.bad, 1u);
 
     // per-event denominators: segmented reduction over the wavefront's rows
     unsigned long long act = __ballot(len > 0);
     while (act) {
       const int leader = __ffsll((long long)act) - 1;
-      const int el = __shfl(e, leader, WAVE);
+      const int el = __builtin_amdgcn_readlane(e, leader);
       const bool mine = len > 0 && e == el;
-      const float v = wave_sum(mine ? D : 0.0f);
-      if (lane == leader) atomicAdd(&bs.D[el], (double)v);
+      const float v = wave_sum_dpp(mine ? D : 0.0f);
+      if (lane == 0) atomicAdd(&ps.D[buf][el], (double)v);
       act &= ~__ballot(mine);
     }
     __syncthreads();
 
     // pass 2: m / D into the region accumulators (2^-32 fixed point)
     {
-      const double Dd = len > 0 ? bs.D[e] : 1.0;
-      if (len > 0 && !(Dd > 0.0) && tid == bs.cum[e]) atomicAdd(&bs.zero, 1u);
+      const double Dd = len > 0 ? ps.D[buf][e] : 1.0;
       const int n2 = Dd > 0.0 ? len : 0;
       // 2^32 / D overflows a float only for D < 1.3e-29; such wavefronts pre-scale m by 2^64
       if (__any(n2 > 0 && Dd < 1e-28)) {
@@ -212,6 +246,11 @@ __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan 
         pass2<MAXLEN, false>(m, sc, base, pitch, n2, wl, acc_s);
       }
     }
+    if (tid < nb && !(ps.D[buf][tid] > 0.0)) atomicAdd(&ps.zero, 1u);
+    if (tid < kMaxBatch) ps.D[buf ^ 1][tid] = 0.0;  // read last two batches ago
+    word = next;
+    wl = wl_next;
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 
@@ -222,14 +261,47 @@ __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan 
     const int cl = q / pitch;
     const int rl = q - cl * pitch;
     const int r = rbase + rl;
-    const int k = kbase + cl + shear_offset(g, tc, r);
+    const int k = kbase + cl + ps.off[rl < p.RY ? rl : 0];
     if (rl < p.RY && r >= 0 && r < g.n_y && k >= 0 && k < g.n_z) atomicAdd(&acc[(int64_t)r * g.n_z + k], a);
   }
   if (tid == 0) {
-    if (bs.zero) atomicAdd(&cnt[C_ZERO_DEN], (unsigned long long)bs.zero);
-    if (bs.bad) atomicAdd(&cnt[C_KAPPA_BAD], (unsigned long long)bs.bad);
-    if (bs.outside) atomicAdd(&cnt[C_OUTSIDE], (unsigned long long)bs.outside);
+    if (ps.zero) atomicAdd(&cnt[C_ZERO_DEN], (unsigned long long)ps.zero);
+    if (ps.bad) atomicAdd(&cnt[C_KAPPA_BAD], (unsigned long long)ps.bad);
   }
+}
+
+template <int MAXLEN, int WAVES>
+__global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan p,
+                                                                    const unsigned char* __restrict__ blocks,
+                                                                    const BinItem* __restrict__ items,
+                                                                    const float* __restrict__ rho,
+                                                                    unsigned long long* __restrict__ acc,
+                                                                    unsigned long long* __restrict__ cnt) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ PassShared ps;
+  if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
+  event_pass_item<MAXLEN, WAVES>(g, p, blocks, items[blockIdx.x], rho, acc, cnt, smem, ps);
+}
+
+// The same pass over many independent reconstructions in one launch: the grid is the
+// concatenation of the instances' work lists (table sorted by item_begin); each workgroup finds
+// its instance by binary search.
+template <int MAXLEN, int WAVES>
+__global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_batched(const BatchInst* __restrict__ inst,
+                                                                      int count) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ PassShared ps;
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = count - 1;  // last instance whose item_begin <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].item_begin <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchInst& I = inst[lo];
+  const int64_t local = b - I.item_begin;
+  if (!I.tiled || local >= (int64_t)I.cnt[C_ITEMS]) return;
+  event_pass_item<MAXLEN, WAVES>(I.g, I.p, I.blocks, I.items[local], I.rho, I.acc, I.cnt, smem, ps);
 }
 
 // Generic pass for geometries whose rows or regions do not fit the tiled pass: one wavefront per
@@ -301,12 +373,87 @@ hipError_t launch_tiled(const Geo& g, const Plan& p, const Workspace& ws, const 
   auto kern = k_event_pass_tiled<MAXLEN, WAVES>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)p.max_items), dim3(64 * p.waves), p.lds_bytes, st, g, p, ws.evs, ws.items,
-                     rho, ws.acc, ws.cnt);
+  hipLaunchKernelGGL(kern, dim3((unsigned)p.max_items), dim3(64 * p.waves), p.lds_bytes, st, g, p, ws.batches,
+                     ws.items, rho, ws.acc, ws.cnt);
   return hipGetLastError();
 }
 
+template <int MAXLEN, int WAVES>
+hipError_t launch_batched(const BatchInst* table, int count, size_t lds_bytes, int64_t grid, hipStream_t st) {
+  auto kern = k_event_pass_batched<MAXLEN, WAVES>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * WAVES), lds_bytes, st, table, count);
+  return hipGetLastError();
+}
+
+__global__ void k_write_insts(InstWrite w, BatchInst* __restrict__ table) {
+  const int t = threadIdx.x;
+  if (t < w.count) table[w.first + t] = w.v[t];
+}
+
+// per-iteration counters of every instance: zero-denominator events, non-positive kappa pairs
+__global__ void k_batched_reset(const BatchInst* __restrict__ table, int count) {
+  for (int k = threadIdx.x; k < count; k += blockDim.x) {
+    table[k].cnt[C_ZERO_DEN] = 0ull;
+    table[k].cnt[C_KAPPA_BAD] = 0ull;
+  }
+}
+
+// rho = acc 2^-32 / s of every instance (blockIdx.y: table entry)
+__global__ void k_update_batched(const BatchInst* __restrict__ table) {
+  const BatchInst& I = table[blockIdx.y];
+  const int64_t npix = (int64_t)I.g.n_y * I.g.n_z;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < npix; q += (int64_t)gridDim.x * blockDim.x) {
+    const double a = (double)I.acc[q] * 2.3283064365386962890625e-10;
+    double v;
+    if (I.s) {
+      const float sv = I.s[q];
+      v = sv > 0.0f ? a / (double)sv : 0.0;
+    } else {
+      v = a;
+    }
+    I.rho[q] = (float)v;
+    I.acc[q] = 0ull;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t st) {
+  hipLaunchKernelGGL(k_write_insts, dim3(1), dim3(64), 0, st, w, table);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_reset(const BatchInst* table, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batched_reset, dim3(1), dim3(256), 0, st, table, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxlen, int waves, size_t lds_bytes,
+                                     int64_t grid, hipStream_t st) {
+  if (count <= 0 || grid <= 0) return hipSuccess;
+  switch (maxlen * 100 + waves) {
+    case 1608: return launch_batched<16, 8>(table, count, lds_bytes, grid, st);
+    case 3208: return launch_batched<32, 8>(table, count, lds_bytes, grid, st);
+    case 4808: return launch_batched<48, 8>(table, count, lds_bytes, grid, st);
+    case 6408: return launch_batched<64, 8>(table, count, lds_bytes, grid, st);
+    case 1616: return launch_batched<16, 16>(table, count, lds_bytes, grid, st);
+    case 3216: return launch_batched<32, 16>(table, count, lds_bytes, grid, st);
+    case 4816: return launch_batched<48, 16>(table, count, lds_bytes, grid, st);
+    case 6416: return launch_batched<64, 16>(table, count, lds_bytes, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_update_batched(const BatchInst* table, int count, int64_t max_npix, hipStream_t st) {
+  if (count <= 0 || max_npix <= 0) return hipSuccess;
+  int64_t bx = (max_npix + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(k_update_batched, dim3((unsigned)bx, (unsigned)count), dim3(256), 0, st, table);
+  return hipGetLastError();
+}
 
 hipError_t launch_event_pass(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
                              hipStream_t st) {

@@ -105,45 +105,55 @@ __global__ void __launch_bounds__(256) k_histogram(const uint32_t* __restrict__ 
   if (j < n && key[j] != kNoBin) atomicAdd(&bin_count[key[j]], 1u);
 }
 
-// Single workgroup: exclusive scans of the bin sizes and of the items per bin.
-__global__ void __launch_bounds__(1024) k_scan(int nbins, int ev_per_wg, const uint32_t* __restrict__ bin_count,
-                                               uint32_t* __restrict__ bin_start, uint32_t* __restrict__ item_start,
+// Single workgroup: exclusive scans of the bin sizes, of the workgroup items per bin and of the
+// batch blocks per bin.
+__global__ void __launch_bounds__(1024) k_scan(int nbins, int ev_per_wg, int ev_per_batch,
+                                               const uint32_t* __restrict__ bin_count, uint32_t* __restrict__ bin_start,
+                                               uint32_t* __restrict__ item_start, uint32_t* __restrict__ batch_start,
                                                unsigned long long* __restrict__ cnt) {
-  __shared__ uint32_t s_ev[1024], s_it[1024];
+  __shared__ uint32_t s_ev[1024], s_it[1024], s_ba[1024];
   const int T = blockDim.x;
   const int chunk = (nbins + T - 1) / T;
   const int lo = min(nbins, (int)threadIdx.x * chunk), hi = min(nbins, lo + chunk);
-  uint32_t se = 0, si = 0;
+  uint32_t se = 0, si = 0, sb = 0;
   for (int b = lo; b < hi; ++b) {
     const uint32_t c = bin_count[b];
     se += c;
     si += (c + ev_per_wg - 1) / ev_per_wg;
+    sb += (c + ev_per_batch - 1) / ev_per_batch;
   }
   s_ev[threadIdx.x] = se;
   s_it[threadIdx.x] = si;
+  s_ba[threadIdx.x] = sb;
   __syncthreads();
   for (int off = 1; off < T; off <<= 1) {
-    uint32_t ae = 0, ai = 0;
+    uint32_t ae = 0, ai = 0, ab = 0;
     if ((int)threadIdx.x >= off) {
       ae = s_ev[threadIdx.x - off];
       ai = s_it[threadIdx.x - off];
+      ab = s_ba[threadIdx.x - off];
     }
     __syncthreads();
     s_ev[threadIdx.x] += ae;
     s_it[threadIdx.x] += ai;
+    s_ba[threadIdx.x] += ab;
     __syncthreads();
   }
-  uint32_t re = threadIdx.x ? s_ev[threadIdx.x - 1] : 0u, ri = threadIdx.x ? s_it[threadIdx.x - 1] : 0u;
+  uint32_t re = threadIdx.x ? s_ev[threadIdx.x - 1] : 0u, ri = threadIdx.x ? s_it[threadIdx.x - 1] : 0u,
+           rb = threadIdx.x ? s_ba[threadIdx.x - 1] : 0u;
   for (int b = lo; b < hi; ++b) {
     const uint32_t c = bin_count[b];
     bin_start[b] = re;
     item_start[b] = ri;
+    batch_start[b] = rb;
     re += c;
     ri += (c + ev_per_wg - 1) / ev_per_wg;
+    rb += (c + ev_per_batch - 1) / ev_per_batch;
   }
   if (threadIdx.x == T - 1) {
     bin_start[nbins] = s_ev[T - 1];
     item_start[nbins] = s_it[T - 1];
+    batch_start[nbins] = s_ba[T - 1];
     cnt[C_ITEMS] = s_it[T - 1];
   }
 }
@@ -159,9 +169,11 @@ __global__ void __launch_bounds__(256) k_scatter(const EventRec* __restrict__ ev
   evs[pos] = ev[j];
 }
 
-__global__ void __launch_bounds__(256) k_items(int nbins, int ev_per_wg, const uint32_t* __restrict__ bin_count,
+__global__ void __launch_bounds__(256) k_items(int nbins, int ev_per_wg, int ev_per_batch,
+                                               const uint32_t* __restrict__ bin_count,
                                                const uint32_t* __restrict__ bin_start,
-                                               const uint32_t* __restrict__ item_start, BinItem* __restrict__ items) {
+                                               const uint32_t* __restrict__ item_start,
+                                               const uint32_t* __restrict__ batch_start, BinItem* __restrict__ items) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbins) return;
   const uint32_t c = bin_count[b];
@@ -171,9 +183,145 @@ __global__ void __launch_bounds__(256) k_items(int nbins, int ev_per_wg, const u
     it.bin = b;
     it.start = (int32_t)(bin_start[b] + s);
     it.count = (int32_t)min((uint32_t)ev_per_wg, c - s);
-    it.pad = 0;
+    it.batch = (int32_t)(batch_start[b] + s / ev_per_batch);
     items[q] = it;
   }
+}
+
+// Batch blocks of the binned pass: one workgroup per item builds, for each batch of ev_per_batch
+// events, the per-event constants and the thread words.  Rows are given to threads so that a
+// wavefront holds rows of nearly equal length: each event's rows are cut into rings of 32 rows
+// around its central row (ring 0: the 32 central rows; ring k: 16 rows above and 16 below ring
+// k-1) and a remainder at its two tips.  Half-wavefront slots take the rings ordered by ring
+// index, then by event, so a wavefront pairs two rings at the same distance from their
+// ellipses' centres; the tips of all events fill the remaining threads.  Within a
+// half-wavefront the rows are consecutive, which keeps the pass's LDS accesses conflict-free.
+constexpr int kBuildBatch = 32;
+constexpr int kBuildSlots = 64;
+
+__global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const EventRec* __restrict__ evs,
+                                                        const BinItem* __restrict__ items,
+                                                        unsigned char* __restrict__ blocks,
+                                                        unsigned long long* __restrict__ cnt) {
+  __shared__ EventRec ev_s[kBuildBatch];
+  __shared__ int K_s[kBuildBatch], top_s[kBuildBatch];
+  __shared__ unsigned char slot_e[kBuildSlots], slot_k[kBuildSlots];
+  __shared__ int tip_cum[kBuildBatch + 1];
+  __shared__ int nslots_s;
+  __shared__ unsigned outside_s;
+  if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;
+  const BinItem it = items[blockIdx.x];
+  const int tz = it.bin % p.ntz;
+  const int rest = it.bin / p.ntz;
+  const int ty = rest % p.nty;
+  const int tb = rest / p.nty;
+  const double tc = bin_slope(p, tb);
+  const int kmin = -max(shear_offset(g, tc, 0), shear_offset(g, tc, g.n_y - 1));
+  const int rbase = ty * p.TY - p.HY;
+  const int kbase = kmin + tz * p.TZ - p.HZ;
+  const int tid = threadIdx.x;
+  const int lane = tid & (WAVE - 1);
+  if (tid == 0) outside_s = 0u;
+  for (int e0 = 0, bi = 0; e0 < it.count; e0 += p.ev_per_batch, ++bi) {
+    const int nb = min(p.ev_per_batch, it.count - e0);
+    unsigned char* blk = blocks + (size_t)(it.batch + bi) * (size_t)p.batch_bytes;
+    EvConst* evc = reinterpret_cast<EvConst*>(blk);
+    uint32_t* words = reinterpret_cast<uint32_t*>(blk + (size_t)p.ev_per_batch * sizeof(EvConst));
+    __syncthreads();
+    if (tid < nb) {
+      const EventRec e = evs[it.start + e0 + tid];
+      ev_s[tid] = e;
+      const int nrows = e.r1 - e.r0 + 1;
+      const int mrow = nrows >> 1;
+      const int K = min(mrow, nrows - mrow) >> 4;
+      K_s[tid] = K;
+      top_s[tid] = mrow - 16 * K;
+      const float t = (float)e.t, c2 = (float)(e.c * e.c), u = (float)g.u, w = (float)g.w, fa = (float)g.fa;
+      EvConst k;
+      k.y = e.y;
+      k.z = e.z;
+      k.t = t;
+      k.A1 = 2.0f * u * c2 * c2;
+      k.A2 = w * fa * fa * c2 * t * t;
+      k.A3 = 4.0f * w * c2 * (1.0f + 2.0f * t * t);
+      k.KB = -4.0f * u * t * c2;
+      k.G1 = 2.0f * fa * w * c2 * t;
+      k.GB = -2.0f * u * c2;
+      k.Q3s = (float)kHalfLog2e * 4.0f * w * c2;
+      k.pad[0] = k.pad[1] = k.pad[2] = k.pad[3] = 0;
+      evc[tid] = k;
+    }
+    __syncthreads();
+    if (tid < WAVE) {  // ring slots (ring-major, then event) and the tip prefix
+      const int K = tid < nb ? K_s[tid] : 0;
+      const int T = tid < nb ? (ev_s[tid].r1 - ev_s[tid].r0 + 1) - 32 * K : 0;
+      const int Kmax = wave_max_i(K);
+      int base_slot = 0;
+      for (int k = 0; k < Kmax; ++k) {
+        const unsigned long long msk = __ballot(K > k);
+        const int before = __popcll(msk & ((1ull << lane) - 1ull));
+        if (K > k) {
+          slot_e[base_slot + before] = (unsigned char)tid;
+          slot_k[base_slot + before] = (unsigned char)k;
+        }
+        base_slot += __popcll(msk);
+      }
+      int incl = T;
+#pragma unroll
+      for (int off = 1; off < WAVE; off <<= 1) {
+        const int o = __shfl_up(incl, off, WAVE);
+        if (lane >= off) incl += o;
+      }
+      if (tid < nb) tip_cum[tid] = incl - T;
+      if (tid == nb - 1) tip_cum[nb] = incl;
+      if (tid == 0) nslots_s = base_slot;
+    }
+    __syncthreads();
+    const int nslots = nslots_s;
+    int e = -1, ri = 0;
+    if (tid < 32 * nslots) {
+      const int sl = tid >> 5, l = tid & 31;
+      e = slot_e[sl];
+      const int k = slot_k[sl];
+      const int mrow = (ev_s[e].r1 - ev_s[e].r0 + 1) >> 1;
+      ri = k == 0 ? mrow - 16 + l : (l < 16 ? mrow - 16 * (k + 1) + l : mrow + 16 * k + (l - 16));
+    } else if (tid - 32 * nslots < tip_cum[nb]) {
+      const int q = tid - 32 * nslots;
+      int lo = 0, hi = nb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tip_cum[mid] <= q) lo = mid; else hi = mid - 1;
+      }
+      e = lo;
+      const int qq = q - tip_cum[e];
+      const int top = top_s[e];
+      ri = qq < top ? qq : ((ev_s[e].r1 - ev_s[e].r0 + 1) >> 1) + 16 * K_s[e] + (qq - top);
+    }
+    uint32_t word = 0u;
+    if (e >= 0) {
+      const EventRec ev = ev_s[e];
+      const int i = ev.r0 + ri;
+      int klo, khi;
+      if (row_interval(g, ev, i, &klo, &khi)) {
+        const int rl = i - rbase;
+        const int kl = klo - shear_offset(g, tc, i) - kbase;
+        const int n = khi - klo + 1;
+        if (rl < 0 || rl >= p.RY || kl < 0 || kl + n > p.W || n > p.maxlen) {
+          atomicAdd(&outside_s, 1u);
+        } else {
+          word = ((uint32_t)kl << kWordCol) | ((uint32_t)rl << kWordRow) | ((uint32_t)n << kWordLen) |
+                 ((uint32_t)e << kWordEv);
+        }
+      }
+    }
+    if (tid < 64 * p.waves) {
+      words[tid] = word;
+      const int wl = wave_max_i((int)((word >> kWordLen) & 127u));
+      if (lane == 0) words[64 * p.waves + (tid >> 6)] = (uint32_t)wl;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && outside_s) atomicAdd(&cnt[C_OUTSIDE], (unsigned long long)outside_s);
 }
 
 int blocks_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
@@ -190,14 +338,18 @@ hipError_t launch_prepare(const Geo& g, const Plan& p, const float* events, int6
   hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(nb, 256)), dim3(256), 0, st, ws.bin_count, nb);
   hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(nb, 256)), dim3(256), 0, st, ws.bin_fill, nb);
   if (n > 0) hipLaunchKernelGGL(k_histogram, dim3(blocks_for(n, 256)), dim3(256), 0, st, ws.key, n, ws.bin_count);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p.nbins, p.ev_per_wg, ws.bin_count, ws.bin_start,
-                     ws.item_start, ws.cnt);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p.nbins, p.ev_per_wg, p.ev_per_batch, ws.bin_count,
+                     ws.bin_start, ws.item_start, ws.batch_start, ws.cnt);
   if (n > 0) {
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, ws.ev, ws.key, n, ws.bin_start,
                        ws.bin_fill, ws.evs);
   }
-  hipLaunchKernelGGL(k_items, dim3(blocks_for(nb, 256)), dim3(256), 0, st, p.nbins, p.ev_per_wg, ws.bin_count,
-                     ws.bin_start, ws.item_start, ws.items);
+  hipLaunchKernelGGL(k_items, dim3(blocks_for(nb, 256)), dim3(256), 0, st, p.nbins, p.ev_per_wg, p.ev_per_batch,
+                     ws.bin_count, ws.bin_start, ws.item_start, ws.batch_start, ws.items);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_build_batches, dim3((unsigned)p.max_items), dim3(64 * p.waves), 0, st, g, p, ws.evs, ws.items,
+                       ws.batches, ws.cnt);
+  }
   return hipGetLastError();
 }
 

@@ -63,6 +63,12 @@ class LaunchInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+class Instance(ctypes.Structure):
+    """One reconstruction of a batch (jpet_instance)."""
+    _fields_ = [("g", Geometry), ("events", ctypes.c_void_p), ("n", ctypes.c_int64), ("s", ctypes.c_void_p),
+                ("rho", ctypes.c_void_p)]
+
+
 _L = None
 
 
@@ -82,8 +88,14 @@ def _lib():
         L.jpet_mlem_workspace_size.argtypes = [gp, i64, ctypes.POINTER(sz)]
         L.jpet_mlem_prepare.argtypes = [gp, vp, i64, vp, sz, vp]
         L.jpet_mlem_iterate.argtypes = [gp, vp, i64, vp, vp, i32, vp, sz, u32, sp, vp]
+        L.jpet_mlem_backproject.argtypes = [gp, vp, i64, vp, vp, vp, sz, u32, sp, vp]
+        L.jpet_mlem_update.argtypes = [gp, vp, vp, vp, vp]
         L.jpet_loglik_grad.argtypes = [gp, ctypes.POINTER(ctypes.c_double), vp, i64, vp, vp, vp, vp, vp, vp, sz,
                                        u32, sp, vp]
+        ip = ctypes.POINTER(Instance)
+        L.jpet_mlem_batched_workspace_size.argtypes = [ip, i32, ctypes.POINTER(sz)]
+        L.jpet_mlem_batched_prepare.argtypes = [ip, i32, vp, sz, vp]
+        L.jpet_mlem_batched_iterate.argtypes = [ip, i32, i32, vp, sz, u32, sp, vp]
         L.jpet_mlem_launch_info.argtypes = [gp, i64, ctypes.POINTER(LaunchInfo)]
         L.jpet_profile_enable.argtypes = [ctypes.c_int]
         L.jpet_profile_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
@@ -201,6 +213,146 @@ def mlem(events: torch.Tensor, g: Geometry, n_iter: int, sens: torch.Tensor | No
     return rho
 
 
+def accumulator(g: Geometry, device=None) -> torch.Tensor:
+    """A zeroed back-projection accumulator (int64 [n_y, n_z], 2^-32 units, read as uint64)."""
+    return torch.zeros(g.shape, dtype=torch.int64, device=device or "cuda")
+
+
+def backproject(g: Geometry, events: torch.Tensor, rho: torch.Tensor, acc: torch.Tensor, ws: torch.Tensor | None = None,
+                prepared: bool = False, want_stats: bool = False, stream=None):
+    """One event pass over this event list, added into acc (see jpet_mlem_backproject)."""
+    _events(events)
+    _need(rho, "rho", torch.float32, g.shape)
+    _need(acc, "acc", torch.int64, g.shape)
+    if ws is None:
+        ws = workspace(g, events.shape[0], rho.device)
+        prepared = False
+    st = Stats() if want_stats else None
+    rc = _lib().jpet_mlem_backproject(ctypes.byref(g), _ptr(events), events.shape[0], _ptr(rho), _ptr(acc), _ptr(ws),
+                                      ws.numel(), JPET_WS_PREPARED if prepared else 0,
+                                      ctypes.byref(st) if st is not None else None, _stream(stream))
+    _check(rc, "jpet_mlem_backproject")
+    return st.as_dict() if st is not None else None
+
+
+def update(g: Geometry, acc: torch.Tensor, rho: torch.Tensor, s: torch.Tensor | None = None, stream=None):
+    """rho = acc 2^-32 / s (0 where s = 0), acc cleared (see jpet_mlem_update)."""
+    _need(rho, "rho", torch.float32, g.shape)
+    _need(acc, "acc", torch.int64, g.shape)
+    if s is not None:
+        _need(s, "s", torch.float32, g.shape)
+    _check(_lib().jpet_mlem_update(ctypes.byref(g), _ptr(s), _ptr(acc), _ptr(rho), _stream(stream)),
+           "jpet_mlem_update")
+
+
+class ChunkedMLEM:
+    """MLEM over an event list held as chunks (device or pinned-host float32 [n_k, 3] tensors).
+
+    Every chunk is back-projected against the same image into one accumulator, then the image is
+    updated once per iteration, so the result equals one jpet_mlem_iterate over the concatenated
+    events (exactly: the accumulator is an integer sum).
+
+    resident=True keeps every chunk's events and prepared workspace in device memory, prepared
+    once (the fast path when they fit: at 288 GB per GPU they usually do).  resident=False keeps
+    one device slot pair and streams the chunks through it every iteration, each copied on a side
+    stream while the previous chunk is processed and prepared again on arrival.
+    """
+
+    def __init__(self, g: Geometry, chunks, s: torch.Tensor | None = None, resident: bool = True, device=None):
+        self.g = g
+        self.s = s
+        self.device = torch.device(device or "cuda")
+        self.resident = resident
+        self.chunks = list(chunks)
+        for c in self.chunks:
+            if c.dim() != 2 or c.shape[1] != 3 or c.dtype != torch.float32:
+                raise ValueError("chunks must be float32 [n, 3]")
+        self.acc = accumulator(g, self.device)
+        self.stats = None
+        if resident:
+            self.ev = [c.to(self.device, non_blocking=True).contiguous() for c in self.chunks]
+            self.ws = [workspace(g, c.shape[0], self.device) for c in self.ev]
+            for e, w in zip(self.ev, self.ws):
+                prepare(g, e, w)
+        else:
+            cap = max((c.shape[0] for c in self.chunks), default=0)
+            self.slots = [torch.empty((cap, 3), dtype=torch.float32, device=self.device) for _ in range(2)]
+            # one workspace, prepared again for each chunk: the largest any chunk needs
+            wsb = max((workspace_size(g, c.shape[0]) for c in self.chunks), default=workspace_size(g, 0))
+            self.ws = [torch.empty(wsb, dtype=torch.uint8, device=self.device)]
+            self.copy_stream = torch.cuda.Stream(device=self.device)
+
+    def iterate(self, rho: torch.Tensor, n_iter: int, want_stats: bool = False):
+        """n_iter iterations in place on rho; the summed stats of the last iteration if asked."""
+        tot = None
+        for it in range(n_iter):
+            last = want_stats and it == n_iter - 1
+            tot = {} if last else None
+            for k in range(len(self.chunks)):
+                ev, ws, prepared = self._chunk(k)
+                st = backproject(self.g, ev, rho, self.acc, ws=ws, prepared=prepared, want_stats=last)
+                if last:
+                    for key, v in st.items():
+                        tot[key] = tot.get(key, 0) + v
+            update(self.g, self.acc, rho, self.s)
+        return tot
+
+    def _chunk(self, k):
+        if self.resident:
+            return self.ev[k], self.ws[k], True
+        cur = torch.cuda.current_stream(self.device)
+        n = self.chunks[k].shape[0]
+        slot = self.slots[k % 2]
+        if k == 0:  # first chunk of the iteration: copy now
+            slot[:n].copy_(self.chunks[0], non_blocking=True)
+        else:
+            cur.wait_stream(self.copy_stream)
+        if k + 1 < len(self.chunks):  # start the next copy once the slot it overwrites is free
+            nxt = self.slots[(k + 1) % 2]
+            m = self.chunks[k + 1].shape[0]
+            self.copy_stream.wait_stream(cur)
+            with torch.cuda.stream(self.copy_stream):
+                nxt[:m].copy_(self.chunks[k + 1], non_blocking=True)
+        return slot[:n], self.ws[0], False
+
+
+class BatchedMLEM:
+    """Many independent reconstructions advanced together (jpet_mlem_batched_*): one event-pass
+    launch per iteration for the whole batch.
+
+    instances: list of (geometry, events float32 [n, 3], sensitivity or None, rho float32 [n_y, n_z]),
+    all CUDA tensors on one device; each rho is updated in place by iterate().  The events are
+    prepared once, here.
+    """
+
+    def __init__(self, instances, stream=None):
+        self.keep = []
+        arr = (Instance * max(len(instances), 1))()
+        for k, (g, ev, s, rho) in enumerate(instances):
+            _events(ev)
+            _need(rho, "rho", torch.float32, g.shape)
+            if s is not None:
+                _need(s, "s", torch.float32, g.shape)
+            arr[k] = Instance(g, ev.data_ptr(), ev.shape[0], s.data_ptr() if s is not None else None, rho.data_ptr())
+            self.keep.append((g, ev, s, rho))
+        self.count = len(instances)
+        self.arr = arr
+        b = ctypes.c_size_t(0)
+        _check(_lib().jpet_mlem_batched_workspace_size(arr, self.count, ctypes.byref(b)),
+               "jpet_mlem_batched_workspace_size")
+        dev = instances[0][3].device if instances else torch.device("cuda")
+        self.ws = torch.empty(max(int(b.value), 256), dtype=torch.uint8, device=dev)
+        _check(_lib().jpet_mlem_batched_prepare(arr, self.count, _ptr(self.ws), self.ws.numel(), _stream(stream)),
+               "jpet_mlem_batched_prepare")
+
+    def iterate(self, n_iter: int, want_stats: bool = False, stream=None):
+        """n_iter iterations of every instance; per-instance stats dicts when want_stats."""
+        st = (Stats * max(self.count, 1))() if want_stats else None
+        _check(_lib().jpet_mlem_batched_iterate(self.arr, self.count, int(n_iter), _ptr(self.ws), self.ws.numel(),
+                                                JPET_WS_PREPARED, st, _stream(stream)), "jpet_mlem_batched_iterate")
+        return [st[k].as_dict() for k in range(self.count)] if want_stats else None
+
+
 @dataclass
 class LogLik:
     value: torch.Tensor        # device double[3]: l, dl/dsigma_z, dl/dsigma_dl
@@ -231,3 +383,50 @@ def loglik_grad(g: Geometry, events: torch.Tensor, rho: torch.Tensor, s: torch.T
     if rc != JPET_EDOMAIN:
         _check(rc, "jpet_loglik_grad")
     return LogLik(out3, gr, D, st.as_dict() if st is not None else None)
+
+
+class JPetLogLik(torch.autograd.Function):
+    """The list-mode log-likelihood l(rho, sigma_z, sigma_dl) of jpet_loglik_grad as a differentiable
+    scalar (float64, on the events' device).
+
+    Forward and backward share one library call: the forward pass evaluates l, dl/drho = B - s and
+    the two sigma derivatives together; backward scales them by the incoming gradient.  The sigma
+    derivatives hold the 3-sigma ellipse fixed (at sigma_mask, default the sigmas given).
+
+        l = JPetLogLik.apply(rho, sigma_z, sigma_dl, events, g, s, sigma_mask)
+
+    rho: float32 [n_y, n_z] CUDA tensor; sigma_z, sigma_dl: Python floats or 0-dim tensors (they
+    override the sigmas of g); s: sensitivity or None; sigma_mask: (sigma_z, sigma_dl) or None.
+    """
+
+    @staticmethod
+    def forward(ctx, rho, sigma_z, sigma_dl, events, g, s=None, sigma_mask=None):
+        sz = float(sigma_z)
+        sd = float(sigma_dl)
+        gg = Geometry(g.R, g.L, sz, sd, g.gamma, g.pixel, g.n_y, g.n_z, g.kernel_variant, 0)
+        mask = (sz, sd) if sigma_mask is None else tuple(float(x) for x in sigma_mask)
+        res = loglik_grad(gg, events, rho.detach().contiguous(), s=s, sigma_mask=mask,
+                          want_grad_rho=ctx.needs_input_grad[0])
+        ctx.save_for_backward(res.value, res.grad_rho if res.grad_rho is not None else torch.empty(0))
+        ctx.sig = [(x.dtype, x.device) if isinstance(x, torch.Tensor) else None for x in (sigma_z, sigma_dl)]
+        return res.value[0].clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        value, grad_rho = ctx.saved_tensors
+        g_rho = g_sz = g_sd = None
+        if ctx.needs_input_grad[0]:
+            g_rho = grad_rho * grad_out.to(grad_rho.dtype)
+        out = []
+        for k, meta in zip((1, 2), ctx.sig):
+            if ctx.needs_input_grad[k] and meta is not None:
+                out.append((grad_out * value[k]).to(dtype=meta[0], device=meta[1]))
+            else:
+                out.append(None)
+        g_sz, g_sd = out
+        return g_rho, g_sz, g_sd, None, None, None, None
+
+
+def loglik(rho, sigma_z, sigma_dl, events, g, s=None, sigma_mask=None):
+    """Differentiable log-likelihood; see JPetLogLik."""
+    return JPetLogLik.apply(rho, sigma_z, sigma_dl, events, g, s, sigma_mask)

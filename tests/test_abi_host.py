@@ -103,6 +103,14 @@ def test_entry_points_reject_bad_arguments_before_any_device_work(lib):
     bad_mask = (ctypes.c_double * 2)(0.0, 63.0)
     assert lib.jpet_loglik_grad(gp, bad_mask, fake, 5, None, fake, fake, None, None, aligned_ws, 1 << 40, 0, None,
                                 None) == jpet.JPET_EDOMAIN
+    # back-projection into a caller accumulator: NULL accumulator, NULL rho, unknown flags, workspace
+    assert lib.jpet_mlem_backproject(gp, fake, 5, fake, None, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_backproject(gp, fake, 5, None, fake, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_backproject(gp, fake, 5, fake, fake, aligned_ws, 1 << 40, 2, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_backproject(gp, fake, 5, fake, fake, aligned_ws, 16, 0, None, None) == jpet.JPET_EWORKSPACE
+    assert lib.jpet_mlem_update(gp, None, None, fake, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_update(gp, None, fake, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_update(None, None, fake, fake, None) == jpet.JPET_EINVAL
 
 
 def test_binding_requires_built_library(monkeypatch, tmp_path):

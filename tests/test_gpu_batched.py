@@ -1,0 +1,121 @@
+"""Batched reconstruction (jpet_mlem_batched_*, BatchedMLEM) against the oracle per instance.
+
+Instances take the geometry, resolution and phantom of the batched workload (grids 128/256/512,
+sigma_z 8..15 mm, sigma_dl 40..90 mm); event counts are cut so the oracle runs in seconds, except
+in the full-size test, which checks every instance's count conservation and the smallest ones
+against the oracle.  Tolerances: relative L2 1e-4 against the FP64 oracle, counts exact.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from jpet_synth import get_workload
+from jpet_synth.configs import batch_instances
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1502_07478_amd import jpet  # noqa: E402
+
+DEV = "cuda"
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _events_of(args):
+    w, n = args
+    return w.events(n)
+
+
+def _oracle_run(args):
+    import oracle as orc
+    kw, ev, n_iter, with_s = args
+    g = orc.geometry(**kw)
+    s = orc.sensitivity(g)
+    rho, st = orc.mlem(g, ev, orc.initial_image(s), n_iter, s=s if with_s else None)
+    return rho, st
+
+
+def _pool_map(fn, jobs, procs=16):
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(min(procs, len(jobs))) as pool:
+        return pool.map(fn, jobs)
+
+
+def _setup(ws_list, with_s):
+    inst, images = [], []
+    for w, ev_np in ws_list:
+        g = jpet.geometry(**w.geometry())
+        s = jpet.sensitivity(g)
+        rho = (s > 0).to(torch.float32)
+        ev = torch.from_numpy(ev_np).to(DEV)
+        inst.append((g, ev, s if with_s else None, rho))
+        images.append(rho)
+    return inst, images
+
+
+@pytest.mark.parametrize("with_s", [True, False])
+def test_batched_small_matches_oracle(with_s):
+    base = batch_instances()[:8]
+    counts = [3000, 0, 2500, 1, 4000, 1700, 3500, 2222]  # includes an empty and a one-event instance
+    ws_list = [(w, w.events(n)) for w, n in zip(base, counts)]
+    # plus the small test grid
+    t = get_workload("tiny")
+    ws_list.append((t.replace(n_events=5000), t.events(5000)))
+    inst, images = _setup(ws_list, with_s)
+    b = jpet.BatchedMLEM(inst)
+    n_iter = 2
+    stats = b.iterate(n_iter, want_stats=True)
+    torch.cuda.synchronize()
+    ref = _pool_map(_oracle_run, [(w.geometry(), ev, n_iter, with_s) for w, ev in ws_list])
+    for k, ((w, ev), (rho_o, sto)) in enumerate(zip(ws_list, ref)):
+        assert stats[k]["n_valid"] == sto["n_valid"], k
+        assert stats[k]["n_pairs"] == sto["n_pairs"], k
+        assert stats[k]["n_unplaced_rows"] == 0, k
+        got = images[k].cpu().numpy()
+        if sto["n_valid"] == 0:
+            assert float(np.abs(got).sum()) == 0.0
+        else:
+            assert rel_l2(got, rho_o) <= 1e-4, (k, w.name)
+
+
+def test_batched_equals_single_instance_calls():
+    base = batch_instances()[:6]
+    ws_list = [(w, w.events(4000)) for w in base]
+    inst, images = _setup(ws_list, True)
+    jpet.BatchedMLEM(inst).iterate(3)
+    for (w, ev_np), got in zip(ws_list, images):
+        g = jpet.geometry(**w.geometry())
+        s = jpet.sensitivity(g)
+        rho = (s > 0).to(torch.float32)
+        jpet.mlem_iterate(g, torch.from_numpy(ev_np).to(DEV), rho, 3, s=s)
+        assert rel_l2(got.cpu().numpy(), rho.cpu().numpy()) <= 1e-6, w.name
+
+
+def test_batch64_full_size():
+    """All 64 instances at their full event counts, one iteration: count conservation for every
+    instance, and the three smallest against the oracle."""
+    base = batch_instances()
+    evs = _pool_map(_events_of, [(w, None) for w in base])
+    ws_list = list(zip(base, evs))
+    print(f"batch64: {sum(len(e) for e in evs)} events generated", flush=True)
+    inst, images = _setup(ws_list, True)
+    b = jpet.BatchedMLEM(inst)
+    stats = b.iterate(1, want_stats=True)
+    torch.cuda.synchronize()
+    print("batch64: GPU iteration done", flush=True)
+    for k, (g, ev, s, rho) in enumerate(inst):
+        st = stats[k]
+        assert st["n_unplaced_rows"] == 0
+        total = float((s.double() * rho.double()).sum())
+        assert total == pytest.approx(st["n_valid"] - st["n_zero_denominator"], rel=1e-6), k
+    small = sorted(range(len(base)), key=lambda k: base[k].n_events)[:3]
+    ref = _pool_map(_oracle_run, [(base[k].geometry(), evs[k], 1, True) for k in small])
+    for k, (rho_o, sto) in zip(small, ref):
+        assert stats[k]["n_pairs"] == sto["n_pairs"]
+        assert rel_l2(images[k].cpu().numpy(), rho_o) <= 1e-4, base[k].name
