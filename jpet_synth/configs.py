@@ -51,10 +51,12 @@ class Workload:
             return ph.random_phantom(self.seed)
         raise ValueError(self.phantom_kind)
 
-    def events(self, n: int | None = None, seed_offset: int = 0) -> np.ndarray:
+    def events(self, n: int | None = None, seed_offset: int = 0, workers: int | None = None) -> np.ndarray:
+        """The first n events (default: all); workers=1 generates in this process (required inside
+        a worker process of a pool)."""
         n = self.n_events if n is None else n
         return simulate_events(self.phantom(), self.R, self.L, self.sigma_z, self.sigma_dl, n,
-                               self.seed + seed_offset)
+                               self.seed + seed_offset, workers=workers)
 
     def geometry(self, **over) -> dict:
         g = dict(R=self.R, L=self.L, sigma_z=self.sigma_z, sigma_dl=self.sigma_dl,

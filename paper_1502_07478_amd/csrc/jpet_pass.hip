@@ -24,7 +24,7 @@ constexpr int kChunk = 4;      // pixels evaluated per branch-free step
 
 struct PassShared {
   EvConst ev[2][kMaxBatch];  // double buffer: the next batch is copied in while this one runs
-  double D[2][kMaxBatch];
+  double D[3][kMaxBatch];    // batch b's denominators in D[b % 3]: filled, read, cleared in turn
   int off[kMaxRows];         // sheared column shift of each region row
   unsigned zero, bad;
 };
@@ -146,6 +146,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   if (tid < kMaxBatch) {
     ps.D[0][tid] = 0.0;
     ps.D[1][tid] = 0.0;
+    ps.D[2][tid] = 0.0;
   }
   if (tid == 0) {
     ps.zero = 0u;
@@ -168,88 +169,101 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  for (int bi = 0, buf = 0; bi < nbatch; ++bi, buf ^= 1) {
-    const int nb = min(p.ev_per_batch, it.count - bi * p.ev_per_batch);
-    // prefetch the next batch: constants into the other LDS buffer, this thread's next word
-    uint32_t next = 0u;
-    int wl_next = 0;
-    if (bi + 1 < nbatch) {
-      const unsigned char* blk = blk0 + (size_t)(bi + 1) * (size_t)p.batch_bytes;
-      copy_consts(blk, ps.ev[buf ^ 1], cbytes, tid);
-      next = reinterpret_cast<const uint32_t*>(blk + cbytes)[tid];
-      wl_next = *reinterpret_cast<const int*>(blk + wl_off);
-    }
-
-    // this thread's row
-    const int len = (int)((word >> kWordLen) & 127u);
-    const int e = (int)((word >> kWordEv) & 31u);
-    int base = 0;
-    bool safe = true;
-    RowF rk = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    if (len > 0) {
-      const int kl = (int)((word >> kWordCol) & 255u);
-      const int rl = (int)((word >> kWordRow) & 511u);
-      const EvConst& c = ps.ev[buf][e];
-      const int i = rbase + rl;
-      const int klo = kl + kbase + ps.off[rl];
-      const double Yd = g.y0 + (double)i * g.pixel;
-      const double dyd = Yd - c.y;
-      const double b10d = g.z0 + (double)klo * g.pixel - (c.z + (double)c.t * dyd);
-      const float Y = (float)Yd, dy = (float)dyd, b10 = (float)b10d;
-      const float kr = fmaf(c.A1, R2 + Y * Y, Y * fmaf(c.A2, Y, c.A3 * dy));
-      const float kb = c.KB * Y;
-      const float gb = c.GB * Y;
-      rk.kap0 = fmaf(kb, b10, kr);
-      rk.dkap = kb * pixf;
-      rk.gs0 = rs * fmaf(gb, b10, c.G1 * Y * dy);
-      rk.dgs = rs * gb * pixf;
-      rk.qb = 2.0f * S2u * b10 * pixf;
-      rk.qc = fmaf(S2u * b10, b10, c.Q3s * dy * dy);
-      const float kend = fmaf((float)(len - 1), rk.dkap, rk.kap0);
-      safe = rk.kap0 > 1e-3f * fabsf(rk.kap0) && kend > 1e-3f * fabsf(rk.kap0);
-      base = kl * pitch + rl;
-    }
-
-    // pass 1: m = P rho along the row, D partial sums
-    float m[MAXLEN];
-    bool bad = false;
-    float D;
-    if (__any(!safe)) {
-      D = pass1<MAXLEN, true>(rk, qa, rho_s, base, pitch, len, wl, m, &bad);
-    } else {
-      D = pass1<MAXLEN, false>(rk, qa, rho_s, base, pitch, len, wl, m, &bad);
-    }
-    if (bad) atomicAdd(&ps.bad, 1u);
-
-    // per-event denominators: segmented reduction over the wavefront's rows
-    unsigned long long act = __ballot(len > 0);
-    while (act) {
-      const int leader = __ffsll((long long)act) - 1;
-      const int el = __builtin_amdgcn_readlane(e, leader);
-      const bool mine = len > 0 && e == el;
-      const float v = wave_sum_dpp(mine ? D : 0.0f);
-      if (lane == 0) atomicAdd(&ps.D[buf][el], (double)v);
-      act &= ~__ballot(mine);
-    }
-    __syncthreads();
-
-    // pass 2: m / D into the region accumulators (2^-32 fixed point)
-    {
-      const double Dd = len > 0 ? ps.D[buf][e] : 1.0;
-      const int n2 = Dd > 0.0 ? len : 0;
+  // Software pipeline, one workgroup barrier per batch: step bi runs pass 2 of batch bi - 1 (its
+  // denominators were completed before the previous barrier) and then pass 1 of batch bi, so
+  // one wavefront's LDS atomics overlap other wavefronts' kernel evaluation.
+  float m[MAXLEN];
+  int plen = 0, pbase = 0, pe = 0, pwl = 0;  // the row held in m (previous batch)
+  for (int bi = 0; bi <= nbatch; ++bi) {
+    // pass 2 of batch bi - 1: m / D into the region accumulators (2^-32 fixed point)
+    if (bi > 0) {
+      const double* Dp = ps.D[(bi - 1) % 3];
+      const double Dd = plen > 0 ? Dp[pe] : 1.0;
+      const int n2 = Dd > 0.0 ? plen : 0;
       // 2^32 / D overflows a float only for D < 1.3e-29; such wavefronts pre-scale m by 2^64
       if (__any(n2 > 0 && Dd < 1e-28)) {
         const float sc = (float)(4294967296.0 / (Dd * 18446744073709551616.0));
-        pass2<MAXLEN, true>(m, sc, base, pitch, n2, wl, acc_s);
+        pass2<MAXLEN, true>(m, sc, pbase, pitch, n2, pwl, acc_s);
       } else {
         const float sc = (float)(4294967296.0 / Dd);
-        pass2<MAXLEN, false>(m, sc, base, pitch, n2, wl, acc_s);
+        pass2<MAXLEN, false>(m, sc, pbase, pitch, n2, pwl, acc_s);
       }
+      const int nbp = min(p.ev_per_batch, it.count - (bi - 1) * p.ev_per_batch);
+      if (tid < nbp && !(Dp[tid] > 0.0)) atomicAdd(&ps.zero, 1u);
     }
-    if (tid < nb && !(ps.D[buf][tid] > 0.0)) atomicAdd(&ps.zero, 1u);
-    if (tid < kMaxBatch) ps.D[buf ^ 1][tid] = 0.0;  // read last two batches ago
-    word = next;
-    wl = wl_next;
+    if (bi < nbatch) {
+      const int buf = bi & 1;
+      // prefetch the next batch: constants into the other LDS buffer, this thread's next word
+      uint32_t next = 0u;
+      int wl_next = 0;
+      if (bi + 1 < nbatch) {
+        const unsigned char* blk = blk0 + (size_t)(bi + 1) * (size_t)p.batch_bytes;
+        copy_consts(blk, ps.ev[buf ^ 1], cbytes, tid);
+        next = reinterpret_cast<const uint32_t*>(blk + cbytes)[tid];
+        wl_next = *reinterpret_cast<const int*>(blk + wl_off);
+      }
+
+      // this thread's row
+      const int len = (int)((word >> kWordLen) & 127u);
+      const int e = (int)((word >> kWordEv) & 31u);
+      int base = 0;
+      bool safe = true;
+      RowF rk = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+      if (len > 0) {
+        const int kl = (int)((word >> kWordCol) & 255u);
+        const int rl = (int)((word >> kWordRow) & 511u);
+        const EvConst& c = ps.ev[buf][e];
+        const int i = rbase + rl;
+        const int klo = kl + kbase + ps.off[rl];
+        const double Yd = g.y0 + (double)i * g.pixel;
+        const double dyd = Yd - c.y;
+        const double b10d = g.z0 + (double)klo * g.pixel - (c.z + (double)c.t * dyd);
+        const float Y = (float)Yd, dy = (float)dyd, b10 = (float)b10d;
+        const float kr = fmaf(c.A1, R2 + Y * Y, Y * fmaf(c.A2, Y, c.A3 * dy));
+        const float kb = c.KB * Y;
+        const float gb = c.GB * Y;
+        rk.kap0 = fmaf(kb, b10, kr);
+        rk.dkap = kb * pixf;
+        rk.gs0 = rs * fmaf(gb, b10, c.G1 * Y * dy);
+        rk.dgs = rs * gb * pixf;
+        rk.qb = 2.0f * S2u * b10 * pixf;
+        rk.qc = fmaf(S2u * b10, b10, c.Q3s * dy * dy);
+        const float kend = fmaf((float)(len - 1), rk.dkap, rk.kap0);
+        safe = rk.kap0 > 1e-3f * fabsf(rk.kap0) && kend > 1e-3f * fabsf(rk.kap0);
+        base = kl * pitch + rl;
+      }
+
+      // pass 1: m = P rho along the row, D partial sums
+      bool bad = false;
+      float D;
+      if (__any(!safe)) {
+        D = pass1<MAXLEN, true>(rk, qa, rho_s, base, pitch, len, wl, m, &bad);
+      } else {
+        D = pass1<MAXLEN, false>(rk, qa, rho_s, base, pitch, len, wl, m, &bad);
+      }
+      if (bad) atomicAdd(&ps.bad, 1u);
+
+      // per-event denominators: segmented reduction over the wavefront's rows
+      double* Dc = ps.D[bi % 3];
+      unsigned long long act = __ballot(len > 0);
+      while (act) {
+        const int leader = __ffsll((long long)act) - 1;
+        const int el = __builtin_amdgcn_readlane(e, leader);
+        const bool mine = len > 0 && e == el;
+        const float v = wave_sum_dpp(mine ? D : 0.0f);
+        if (lane == 0) atomicAdd(&Dc[el], (double)v);
+        act &= ~__ballot(mine);
+      }
+      // batch bi + 1 accumulates into D[(bi + 1) % 3], last read (as batch bi - 2's) before the
+      // previous barrier
+      if (tid < kMaxBatch) ps.D[(bi + 1) % 3][tid] = 0.0;
+      plen = len;
+      pbase = base;
+      pe = e;
+      pwl = wl;
+      word = next;
+      wl = wl_next;
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }

@@ -29,7 +29,7 @@ def rel_l2(a, b):
 
 def _events_of(args):
     w, n = args
-    return w.events(n)
+    return w.events(n, workers=1)
 
 
 def _oracle_run(args):
