@@ -193,8 +193,8 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
   {
     const int epb = (64 * p.waves) / rows_max;
     p.ev_per_batch = epb < 32 ? epb : 32;
-    p.batch_bytes =
-        (int)((p.ev_per_batch * sizeof(EvConst) + 4u * 65u * (unsigned)p.waves + 255u) / 256u * 256u);
+    p.batch_bytes = (int)((p.ev_per_batch * sizeof(EvConst) + 4u * (64u + kBlockTailWords) * (unsigned)p.waves + 255u) /
+                          256u * 256u);
   }
   p.nty = (g->n_y + p.TY - 1) / p.TY;
   // sheared column span: the widest over the t bins
@@ -209,10 +209,11 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
   }
   p.ntz = (span + p.TZ - 1) / p.TZ;
   p.nbins = p.ntb * p.nty * p.ntz;
-  // events per workgroup item: enough items to fill the chip, at most 32 batches
+  // events per workgroup item: enough items to fill the chip, at most 128 batches (the region's
+  // staging and flush are amortised over the item)
   int64_t per = n / 1024;
   if (per < p.ev_per_batch) per = p.ev_per_batch;
-  if (per > 32 * p.ev_per_batch) per = 32 * p.ev_per_batch;
+  if (per > 128 * p.ev_per_batch) per = 128 * p.ev_per_batch;
   p.ev_per_wg = (int)((per / p.ev_per_batch) * p.ev_per_batch);
   const int64_t nonempty = n < p.nbins ? n : p.nbins;
   p.max_items = (n + p.ev_per_wg - 1) / p.ev_per_wg + nonempty;

@@ -38,7 +38,8 @@ struct EventRec {
 //   gamma = bC^-1a           = G1 Y dy + GB Y b1
 //   S q   = S bC^-1b         = S 2u b1^2 + Q3s dy^2            (S = log2(e) / 2)
 struct EvConst {
-  double y, z;          // y~, z~
+  float yr, zr;         // y~ and z~ relative to the centre of the bin region's pixel (0, 0)
+  int32_t pad0[2];
   float t;              // tan(theta~)
   float A1, A2, A3, KB; // 2u c^4, w fa^2 c^2 t^2, 4 w c^2 (1 + 2t^2), -4 u t c^2
   float G1, GB, Q3s;    // 2 fa w c^2 t, -2 u c^2, S 4 w c^2
@@ -51,6 +52,10 @@ static_assert(sizeof(EvConst) == 64, "EvConst is copied to LDS in 16-byte units"
 // region: bits 0-7 first column (sheared, region-local), 8-16 row (region-local), 17-23 pixel
 // count (0: idle thread), 24-28 event within the batch.
 constexpr uint32_t kWordCol = 0, kWordRow = 8, kWordLen = 17, kWordEv = 24;
+
+// A batch block: ev_per_batch EvConst, then one thread word per thread of the workgroup, then for
+// each wavefront its longest row and its shortest non-empty row (pixels).
+constexpr int kBlockTailWords = 2;
 
 // Spatial binning of events and launch shape of the tiled event pass.
 //
@@ -66,8 +71,7 @@ struct Plan {
   int HY, HZ;           // halo (rows, columns)
   int RY, W;            // region rows and width
   int pitch;            // LDS row pitch of a region column (RY rounded up to the bank count)
-  int batch_bytes;      // stride of a batch block: ev_per_batch EvConst, 64 * waves thread words, then
-                        // the longest row of each wavefront (waves ints)
+  int batch_bytes;      // stride of a batch block (see kBlockTailWords)
   int ntb, nty, ntz;    // bins along t, y, z
   int nbins;
   double tmin, dt;      // t bin b spans [tmin + b dt, tmin + (b+1) dt); ntb == 1: no shear

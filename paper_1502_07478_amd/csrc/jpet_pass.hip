@@ -37,9 +37,11 @@ struct RowF {
   float kap0, dkap, gs0, dgs, qb, qc;
 };
 
+// Pass 1 along one row.  Chunks below the wavefront's shortest row (wmin, uniform) need no row-end
+// mask; idle lanes carry row constants that make every kernel value 0.
 template <int MAXLEN, bool GUARD>
 __device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __restrict__ rho_s, int base, int pitch,
-                                       int len, int wl, float (&m)[MAXLEN], bool* bad) {
+                                       int len, int wmin, int wl, float (&m)[MAXLEN], bool* bad) {
   float D = 0.0f;
 #pragma unroll
   for (int j0 = 0; j0 < MAXLEN; j0 += kChunk) {
@@ -47,25 +49,42 @@ __device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __
       float r[kChunk];
 #pragma unroll
       for (int jj = 0; jj < kChunk; ++jj) r[jj] = rho_s[base + (j0 + jj) * pitch];
+      if (!GUARD && j0 + kChunk <= wmin) {  // wavefront-uniform: every active lane's row is longer
 #pragma unroll
-      for (int jj = 0; jj < kChunk; ++jj) {
-        const int j = j0 + jj;
-        const float jf = (float)j;
-        float kap = fmaf(jf, rk.dkap, rk.kap0);
-        bool keep = j < len;
-        if (GUARD && !(kap > 0.0f)) {
-          if (keep) *bad = true;
-          keep = false;
-          kap = 1.0f;
+        for (int jj = 0; jj < kChunk; ++jj) {
+          const int j = j0 + jj;
+          const float jf = (float)j;
+          const float kap = fmaf(jf, rk.dkap, rk.kap0);
+          const float gs = fmaf(jf, rk.dgs, rk.gs0);
+          const float rq = __builtin_amdgcn_rsqf(kap);
+          const float sq = fmaf(fmaf(qa, jf, rk.qb), jf, rk.qc);
+          const float tg = gs * rq;
+          const float pv = rq * __builtin_amdgcn_exp2f(fmaf(tg, tg, -sq));
+          const float v = pv * r[jj];
+          m[j] = v;
+          D += v;
         }
-        const float gs = fmaf(jf, rk.dgs, rk.gs0);
-        const float rq = __builtin_amdgcn_rsqf(kap);
-        const float sq = fmaf(fmaf(qa, jf, rk.qb), jf, rk.qc);
-        const float tg = gs * rq;
-        const float pv = rq * __builtin_amdgcn_exp2f(fmaf(tg, tg, -sq));
-        const float v = keep ? pv * r[jj] : 0.0f;
-        m[j] = v;
-        D += v;
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < kChunk; ++jj) {
+          const int j = j0 + jj;
+          const float jf = (float)j;
+          float kap = fmaf(jf, rk.dkap, rk.kap0);
+          bool keep = j < len;
+          if (GUARD && !(kap > 0.0f)) {
+            if (keep) *bad = true;
+            keep = false;
+            kap = 1.0f;
+          }
+          const float gs = fmaf(jf, rk.dgs, rk.gs0);
+          const float rq = __builtin_amdgcn_rsqf(kap);
+          const float sq = fmaf(fmaf(qa, jf, rk.qb), jf, rk.qc);
+          const float tg = gs * rq;
+          const float pv = rq * __builtin_amdgcn_exp2f(fmaf(tg, tg, -sq));
+          const float v = keep ? pv * r[jj] : 0.0f;
+          m[j] = v;
+          D += v;
+        }
       }
     } else {
 #pragma unroll
@@ -75,13 +94,17 @@ __device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __
   return D;
 }
 
+// Pass 2 along one row: m sc rounded into the 64-bit accumulators.  Below wmin every lane adds
+// (idle lanes and lanes with D = 0 add 0 at a valid address); above it the row end masks.
 template <int MAXLEN, bool PRESCALE>
-__device__ __forceinline__ void pass2(const float (&m)[MAXLEN], float sc, int base, int pitch, int len, int wl,
-                                      unsigned long long* __restrict__ acc_s) {
+__device__ __forceinline__ void pass2(const float (&m)[MAXLEN], float sc, int base, int pitch, int len, int wmin,
+                                      int wl, unsigned long long* __restrict__ acc_s) {
 #pragma unroll
   for (int j = 0; j < MAXLEN; ++j) {
-    if (j < wl && j < len) {
-      const float x = PRESCALE ? m[j] * 18446744073709551616.0f : m[j];
+    const float x = PRESCALE ? m[j] * 18446744073709551616.0f : m[j];
+    if (j < wmin) {  // wavefront-uniform
+      atomicAdd(&acc_s[base + j * pitch], (unsigned long long)(unsigned)fmaf(x, sc, 0.5f));
+    } else if (j < wl && j < len) {
       atomicAdd(&acc_s[base + j * pitch], (unsigned long long)(unsigned)fmaf(x, sc, 0.5f));
     }
   }
@@ -139,10 +162,12 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wl_off = cbytes + 4 * 64 * WAVES + 4 * wave;  // this wavefront's longest row
-  // first batch: constants to LDS, this thread's word and its wavefront's longest row
+  const int wn_off = wl_off + 4 * WAVES;                   // and its shortest non-empty row
+  // first batch: constants to LDS, this thread's word and its wavefront's row lengths
   copy_consts(blk0, ps.ev[0], cbytes, tid);
   uint32_t word = reinterpret_cast<const uint32_t*>(blk0 + cbytes)[tid];
   int wl = *reinterpret_cast<const int*>(blk0 + wl_off);
+  int wn = *reinterpret_cast<const int*>(blk0 + wn_off);
   if (tid < kMaxBatch) {
     ps.D[0][tid] = 0.0;
     ps.D[1][tid] = 0.0;
@@ -152,19 +177,23 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
     ps.zero = 0u;
     ps.bad = 0u;
   }
-  // stage the region of the current image (column-major), clear the accumulators
+  // stage the region of the current image (column-major), clear the accumulators: wavefronts take
+  // columns, lanes take rows
   for (int r = tid; r < p.RY; r += blockDim.x) ps.off[r] = shear_offset(g, tc, rbase + r);
-  for (int q = tid; q < npx; q += blockDim.x) {
-    const int cl = q / pitch;
-    const int rl = q - cl * pitch;
-    const int r = rbase + rl;
-    float v = 0.0f;
-    if (rl < p.RY && r >= 0 && r < g.n_y) {
-      const int k = kbase + cl + shear_offset(g, tc, r);
-      if (k >= 0 && k < g.n_z) v = rho[(int64_t)r * g.n_z + k];
+  __syncthreads();
+  for (int cl = wave; cl < p.W; cl += WAVES) {
+    const int kc = kbase + cl;
+    for (int rl = lane; rl < pitch; rl += WAVE) {
+      const int q = cl * pitch + rl;
+      const int r = rbase + rl;
+      float v = 0.0f;
+      if (rl < p.RY && r >= 0 && r < g.n_y) {
+        const int k = kc + ps.off[rl];
+        if (k >= 0 && k < g.n_z) v = rho[(int64_t)r * g.n_z + k];
+      }
+      rho_s[q] = v;
+      acc_s[q] = 0ull;
     }
-    rho_s[q] = v;
-    acc_s[q] = 0ull;
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -173,7 +202,8 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   // denominators were completed before the previous barrier) and then pass 1 of batch bi, so
   // one wavefront's LDS atomics overlap other wavefronts' kernel evaluation.
   float m[MAXLEN];
-  int plen = 0, pbase = 0, pe = 0, pwl = 0;  // the row held in m (previous batch)
+  int plen = 0, pbase = 0, pe = 0, pwl = 0, pwn = 0;  // the row held in m (previous batch)
+  const float Yb = (float)(g.y0 + (double)rbase * g.pixel);  // y of the region's first row
   for (int bi = 0; bi <= nbatch; ++bi) {
     // pass 2 of batch bi - 1: m / D into the region accumulators (2^-32 fixed point)
     if (bi > 0) {
@@ -182,11 +212,11 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       const int n2 = Dd > 0.0 ? plen : 0;
       // 2^32 / D overflows a float only for D < 1.3e-29; such wavefronts pre-scale m by 2^64
       if (__any(n2 > 0 && Dd < 1e-28)) {
-        const float sc = (float)(4294967296.0 / (Dd * 18446744073709551616.0));
-        pass2<MAXLEN, true>(m, sc, pbase, pitch, n2, pwl, acc_s);
+        const float sc = n2 > 0 ? (float)(4294967296.0 / (Dd * 18446744073709551616.0)) : 0.0f;
+        pass2<MAXLEN, true>(m, sc, pbase, pitch, n2, pwn, pwl, acc_s);
       } else {
-        const float sc = (float)(4294967296.0 / Dd);
-        pass2<MAXLEN, false>(m, sc, pbase, pitch, n2, pwl, acc_s);
+        const float sc = n2 > 0 ? 4294967296.0f * __builtin_amdgcn_rcpf((float)Dd) : 0.0f;
+        pass2<MAXLEN, false>(m, sc, pbase, pitch, n2, pwn, pwl, acc_s);
       }
       const int nbp = min(p.ev_per_batch, it.count - (bi - 1) * p.ev_per_batch);
       if (tid < nbp && !(Dp[tid] > 0.0)) atomicAdd(&ps.zero, 1u);
@@ -195,12 +225,13 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       const int buf = bi & 1;
       // prefetch the next batch: constants into the other LDS buffer, this thread's next word
       uint32_t next = 0u;
-      int wl_next = 0;
+      int wl_next = 0, wn_next = 0;
       if (bi + 1 < nbatch) {
         const unsigned char* blk = blk0 + (size_t)(bi + 1) * (size_t)p.batch_bytes;
         copy_consts(blk, ps.ev[buf ^ 1], cbytes, tid);
         next = reinterpret_cast<const uint32_t*>(blk + cbytes)[tid];
         wl_next = *reinterpret_cast<const int*>(blk + wl_off);
+        wn_next = *reinterpret_cast<const int*>(blk + wn_off);
       }
 
       // this thread's row
@@ -208,17 +239,16 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       const int e = (int)((word >> kWordEv) & 31u);
       int base = 0;
       bool safe = true;
-      RowF rk = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+      RowF rk = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 1e30f};  // idle lane: every kernel value is 0
       if (len > 0) {
         const int kl = (int)((word >> kWordCol) & 255u);
         const int rl = (int)((word >> kWordRow) & 511u);
         const EvConst& c = ps.ev[buf][e];
-        const int i = rbase + rl;
-        const int klo = kl + kbase + ps.off[rl];
-        const double Yd = g.y0 + (double)i * g.pixel;
-        const double dyd = Yd - c.y;
-        const double b10d = g.z0 + (double)klo * g.pixel - (c.z + (double)c.t * dyd);
-        const float Y = (float)Yd, dy = (float)dyd, b10 = (float)b10d;
+        // region-relative coordinates: the row's y, y - y~, and z of its first pixel - z~ - t (y - y~)
+        const float rlf = (float)rl;
+        const float Y = fmaf(rlf, pixf, Yb);
+        const float dy = fmaf(rlf, pixf, -c.yr);
+        const float b10 = fmaf((float)(kl + ps.off[rl]), pixf, -fmaf(c.t, dy, c.zr));
         const float kr = fmaf(c.A1, R2 + Y * Y, Y * fmaf(c.A2, Y, c.A3 * dy));
         const float kb = c.KB * Y;
         const float gb = c.GB * Y;
@@ -237,9 +267,9 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       bool bad = false;
       float D;
       if (__any(!safe)) {
-        D = pass1<MAXLEN, true>(rk, qa, rho_s, base, pitch, len, wl, m, &bad);
+        D = pass1<MAXLEN, true>(rk, qa, rho_s, base, pitch, len, wn, wl, m, &bad);
       } else {
-        D = pass1<MAXLEN, false>(rk, qa, rho_s, base, pitch, len, wl, m, &bad);
+        D = pass1<MAXLEN, false>(rk, qa, rho_s, base, pitch, len, wn, wl, m, &bad);
       }
       if (bad) atomicAdd(&ps.bad, 1u);
 
@@ -261,22 +291,25 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       pbase = base;
       pe = e;
       pwl = wl;
+      pwn = wn;
       word = next;
       wl = wl_next;
+      wn = wn_next;
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 
-  // add the region's accumulators to the global image
-  for (int q = tid; q < npx; q += blockDim.x) {
-    const unsigned long long a = acc_s[q];
-    if (a == 0ull) continue;
-    const int cl = q / pitch;
-    const int rl = q - cl * pitch;
-    const int r = rbase + rl;
-    const int k = kbase + cl + ps.off[rl < p.RY ? rl : 0];
-    if (rl < p.RY && r >= 0 && r < g.n_y && k >= 0 && k < g.n_z) atomicAdd(&acc[(int64_t)r * g.n_z + k], a);
+  // add the region's accumulators to the global image (wavefronts take columns, lanes rows)
+  for (int cl = wave; cl < p.W; cl += WAVES) {
+    const int kc = kbase + cl;
+    for (int rl = lane; rl < p.RY; rl += WAVE) {
+      const unsigned long long a = acc_s[cl * pitch + rl];
+      if (a == 0ull) continue;
+      const int r = rbase + rl;
+      const int k = kc + ps.off[rl];
+      if (r >= 0 && r < g.n_y && k >= 0 && k < g.n_z) atomicAdd(&acc[(int64_t)r * g.n_z + k], a);
+    }
   }
   if (tid == 0) {
     if (ps.zero) atomicAdd(&cnt[C_ZERO_DEN], (unsigned long long)ps.zero);

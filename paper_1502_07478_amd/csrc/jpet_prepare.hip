@@ -238,8 +238,9 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
       top_s[tid] = mrow - 16 * K;
       const float t = (float)e.t, c2 = (float)(e.c * e.c), u = (float)g.u, w = (float)g.w, fa = (float)g.fa;
       EvConst k;
-      k.y = e.y;
-      k.z = e.z;
+      k.yr = (float)(e.y - (g.y0 + (double)rbase * g.pixel));
+      k.zr = (float)(e.z - (g.z0 + (double)kbase * g.pixel));
+      k.pad0[0] = k.pad0[1] = 0;
       k.t = t;
       k.A1 = 2.0f * u * c2 * c2;
       k.A2 = w * fa * fa * c2 * t * t;
@@ -316,8 +317,13 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
     }
     if (tid < 64 * p.waves) {
       words[tid] = word;
-      const int wl = wave_max_i((int)((word >> kWordLen) & 127u));
-      if (lane == 0) words[64 * p.waves + (tid >> 6)] = (uint32_t)wl;
+      const int len = (int)((word >> kWordLen) & 127u);
+      const int wl = wave_max_i(len);
+      const int wmin = -wave_max_i(len > 0 ? -len : -wl);  // shortest non-empty row (0: none)
+      if (lane == 0) {
+        words[64 * p.waves + (tid >> 6)] = (uint32_t)wl;
+        words[65 * p.waves + (tid >> 6)] = (uint32_t)wmin;
+      }
     }
   }
   __syncthreads();
