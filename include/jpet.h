@@ -118,7 +118,8 @@ int jpet_sensitivity(const jpet_geometry* g, float* s_out, void* stream);
 
 /* Bytes of workspace that jpet_mlem_prepare / jpet_mlem_iterate / jpet_loglik_grad need for
  * n_events events on this geometry (host output *bytes).  The workspace is any device
- * allocation of at least that size, aligned to 256 bytes. */
+ * allocation of at least that size, aligned to 256 bytes.  For jpet_loglik_grad with a
+ * sigma_mask, pass a geometry whose sigmas are the mask's (the layout follows the mask). */
 int jpet_mlem_workspace_size(const jpet_geometry* g, int64_t n_events, size_t* bytes);
 
 /* Iteration-invariant per-event work, done once per event list: direct reconstruction (Eq. 2),
@@ -171,7 +172,10 @@ int jpet_mlem_update(const jpet_geometry* g, const float* s, uint64_t* acc, floa
  *   D_out:    device float [n] per-event D_j (0 for dropped events) or NULL
  *   s:        as for jpet_mlem_iterate (NULL = 1)
  * When a valid event has D_j = 0 the device value l is -inf; if stats is given (the call then
- * synchronises) the call also returns JPET_EDOMAIN in that case. */
+ * synchronises) the call also returns JPET_EDOMAIN in that case.
+ * flags = JPET_WS_PREPARED reuses a workspace from jpet_mlem_prepare with this geometry; it is
+ * refused (JPET_EINVAL) when sigma_mask differs from the geometry's sigmas, because the prepared
+ * kernel constants belong to the sigmas the workspace was prepared with. */
 int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const float* events, int64_t n,
                      const float* s, const float* rho, double* out3, float* grad_rho, float* D_out, void* ws,
                      size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream);
@@ -217,7 +221,8 @@ typedef struct jpet_launch_info {
   int32_t row_cache;     /* pixels of a row held in registers between the two passes */
   int32_t events_per_batch;
   int32_t events_per_workgroup;
-  int32_t reserved;
+  int32_t accumulator_bits; /* 64: 2^-32 fixed-point LDS accumulators; 32: 2^-24 ones (regions that
+                               do not fit otherwise); the image accumulator is 64-bit either way */
   double t_bin_width;    /* width of a tan(theta~) bin */
   int64_t lds_bytes;     /* dynamic LDS per workgroup */
   int64_t max_workgroups;/* launch grid of the event pass */

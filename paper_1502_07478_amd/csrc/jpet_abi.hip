@@ -113,89 +113,13 @@ int do_prepare(const Geo& geo, const Plan& p, const float* events, int64_t n, co
 // LDS row-pitch alignment of the binned pass's column-major region
 static const int kBankAlign = 64;
 
-Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int force_waves) {
-  Plan p;
-  memset(&p, 0, sizeof(p));
-  p.ntb = 1;
-  p.dt = 1.0;
+// Derived fields of a binned plan whose region (waves, acc32, tile, halo, t bins) is set.
+static void finish_plan(const jpet_geometry* g, int rows_max, int64_t n, Plan& p) {
   const double pix = g->pixel;
-  const double hy_px = 1.5 * mdl / pix;                 // largest half height of an ellipse (rows)
-  const double chord_px = 2.0 * 3.0 * msz / sqrt(2.0) / pix;  // longest chord along z (columns)
-  const int maxrow = (int)floor(chord_px) + 1;
-  const int rows_max = (int)floor(2.0 * hy_px) + 1;
-  const double tmax = 0.5 * g->L / g->R;               // |tan| of any valid event
-  int maxlen = 0;
-  for (int c : {16, 32, 48, 64})
-    if (maxrow <= c) {
-      maxlen = c;
-      break;
-    }
-  if (maxlen == 0 || rows_max > 64 * 16) return p;  // generic pass
-  p.maxlen = maxlen;
-  p.HY = (int)ceil(hy_px + 0.5) + 1;
-  // Candidates, best first: 8-wave workgroups whose region fits two per CU, then 16-wave
-  // workgroups with one region per CU; for each, no shear, then t bins of decreasing width;
-  // tiles of decreasing size.
-  const int wave_opts[] = {8, 16};
-  // dynamic LDS per workgroup: two 8-wave workgroups per CU, or one 16-wave workgroup (160 KB per
-  // CU, less the static batch buffers)
-  const size_t budget[] = {72 * 1024, 150 * 1024};
-  const double dts[] = {0.0, 0.4, 0.2, 0.1, 0.05, 0.025};
-  const int tiles[] = {32, 24, 16, 12, 8};
-  bool found = false;
-  for (int wi = 0; wi < 2 && !found; ++wi) {
-    const int waves = wave_opts[wi];
-    if (rows_max > 64 * waves || (force_waves && waves != force_waves)) continue;
-    for (double dt : dts) {
-      // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
-      const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
-      const double hz = 3.0 * sqrt(0.5 * msz * msz + 0.25 * mdl * mdl * tau * tau);
-      const int HZ = (int)ceil(hz / pix + 1.0) + 1;
-      for (int T : tiles) {
-        // LDS: float image and 64-bit accumulators, column-major with the row pitch rounded up
-        // to the bank alignment; masked reads up to maxlen columns past the image must stay in
-        // the accumulator array (2 W >= maxlen)
-        const int RY = T + 2 * p.HY, W = T + 2 * HZ;
-        const int pitch = (RY + kBankAlign - 1) / kBankAlign * kBankAlign;
-        const size_t bytes = (size_t)pitch * (size_t)W * 12u;
-        // thread words address columns with 8 bits and rows with 9 bits
-        if (bytes > budget[wi] || 2 * W < maxlen || W > 256 || RY > 512) continue;
-        p.pitch = pitch;
-        p.waves = waves;
-        p.TY = T;
-        p.TZ = T;
-        p.HZ = HZ;
-        p.RY = RY;
-        p.W = W;
-        p.lds_bytes = bytes;
-        if (dt == 0.0) {
-          p.ntb = 1;
-          p.tmin = 0.0;
-          p.dt = 1.0;
-        } else {
-          p.ntb = (int)ceil(2.0 * tmax / dt);
-          if (p.ntb < 1) p.ntb = 1;
-          p.dt = dt;
-          p.tmin = -0.5 * dt * p.ntb;
-        }
-        found = true;
-        break;
-      }
-      if (found) break;
-    }
-  }
-  if (!found) {
-    memset(&p, 0, sizeof(p));
-    p.ntb = 1;
-    p.dt = 1.0;
-    return p;
-  }
-  {
-    const int epb = (64 * p.waves) / rows_max;
-    p.ev_per_batch = epb < 32 ? epb : 32;
-    p.batch_bytes = (int)((p.ev_per_batch * sizeof(EvConst) + 4u * (64u + kBlockTailWords) * (unsigned)p.waves + 255u) /
-                          256u * 256u);
-  }
+  const int epb = (64 * p.waves) / rows_max;
+  p.ev_per_batch = epb < 32 ? epb : 32;
+  p.batch_bytes =
+      (int)((p.ev_per_batch * sizeof(EvConst) + 4u * (64u + kBlockTailWords) * (unsigned)p.waves + 255u) / 256u * 256u);
   p.nty = (g->n_y + p.TY - 1) / p.TY;
   // sheared column span: the widest over the t bins
   int span = g->n_z;
@@ -214,6 +138,9 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
   int64_t per = n / 1024;
   if (per < p.ev_per_batch) per = p.ev_per_batch;
   if (per > 128 * p.ev_per_batch) per = 128 * p.ev_per_batch;
+  // 32-bit accumulators hold 2^-24 units: one event adds at most 2^24 to a pixel, so an item's
+  // events must number below 256 to rule out overflow before the flush
+  if (p.acc32 && per > 255) per = 255;
   p.ev_per_wg = (int)((per / p.ev_per_batch) * p.ev_per_batch);
   const int64_t nonempty = n < p.nbins ? n : p.nbins;
   p.max_items = (n + p.ev_per_wg - 1) / p.ev_per_wg + nonempty;
@@ -221,7 +148,98 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
   p.max_batches = (n + p.ev_per_batch - 1) / p.ev_per_batch + nonempty;
   if (p.max_batches < 1) p.max_batches = 1;
   p.tiled = 1;
-  return p;
+}
+
+Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int force_waves) {
+  Plan none;
+  memset(&none, 0, sizeof(none));
+  none.ntb = 1;
+  none.dt = 1.0;
+  const double pix = g->pixel;
+  const double hy_px = 1.5 * mdl / pix;                 // largest half height of an ellipse (rows)
+  const double chord_px = 2.0 * 3.0 * msz / sqrt(2.0) / pix;  // longest chord along z (columns)
+  const int maxrow = (int)floor(chord_px) + 1;
+  const int rows_max = (int)floor(2.0 * hy_px) + 1;
+  const double tmax = 0.5 * g->L / g->R;               // |tan| of any valid event
+  int maxlen = 0;
+  for (int c : {16, 32, 48, 64})
+    if (maxrow <= c) {
+      maxlen = c;
+      break;
+    }
+  if (maxlen == 0 || rows_max > 64 * 16) return none;  // generic pass
+  const int HY = (int)ceil(hy_px + 0.5) + 1;
+  // Candidate regions: 8-wave workgroups whose region fits two per CU; 16-wave workgroups with
+  // one region per CU; the same with 32-bit accumulators (8 bytes per region pixel instead of 12).
+  // For each: no shear or t bins of a given width, square tiles of a given size.  Dynamic LDS
+  // budgets leave room for the static batch buffers within the CU's 160 KB.
+  //
+  // The cheapest candidate under a simple cost model wins, in units of (event, pixel) pairs:
+  //   pairs of all events (an ellipse's area at theta = 0) x (1.1 for 16-wave workgroups)
+  //   + 1.6 x region pixels x workgroup items,
+  // the second term being the staging of the image region and the flush of its accumulators
+  // (measured at about 1.6 pair evaluations per region pixel); items are the events over the
+  // events per item plus, at most, one partial item per bin.
+  struct Cand {
+    int waves;
+    size_t budget;
+    int acc32;
+  };
+  const Cand cands[] = {{8, 72 * 1024, 0}, {16, 150 * 1024, 0}, {16, 150 * 1024, 1}};
+  const double dts[] = {0.0, 0.4, 0.2, 0.1, 0.05, 0.025};
+  const int tiles[] = {32, 24, 16, 12, 8};
+  const double pairs_per_event = 3.14159265358979323846 * hy_px * (3.0 * msz / sqrt(2.0) / pix);
+  const double nn = (double)(n > 0 ? n : 1);
+  Plan best = none;
+  double best_cost = 0.0;
+  for (const Cand& cd : cands) {
+    const int waves = cd.waves;
+    if (rows_max > 64 * waves || (force_waves && waves != force_waves)) continue;
+    for (double dt : dts) {
+      // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
+      const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
+      const double hz = 3.0 * sqrt(0.5 * msz * msz + 0.25 * mdl * mdl * tau * tau);
+      const int HZ = (int)ceil(hz / pix + 1.0) + 1;
+      for (int T : tiles) {
+        // LDS: float image, then the accumulators, column-major with the row pitch rounded up to
+        // the bank alignment; masked reads up to maxlen columns past the image must stay in the
+        // accumulator array (W columns of 4 or 8 bytes)
+        const int RY = T + 2 * HY, W = T + 2 * HZ;
+        const int pitch = (RY + kBankAlign - 1) / kBankAlign * kBankAlign;
+        const size_t bytes = (size_t)pitch * (size_t)W * (cd.acc32 ? 8u : 12u);
+        const int reach = cd.acc32 ? W : 2 * W;
+        // thread words address columns with 8 bits and rows with 9 bits
+        if (bytes > cd.budget || reach < maxlen || W > 256 || RY > 512) continue;
+        Plan p = none;
+        p.maxlen = maxlen;
+        p.HY = HY;
+        p.pitch = pitch;
+        p.waves = waves;
+        p.acc32 = cd.acc32;
+        p.TY = T;
+        p.TZ = T;
+        p.HZ = HZ;
+        p.RY = RY;
+        p.W = W;
+        p.lds_bytes = bytes;
+        if (dt != 0.0) {
+          p.ntb = (int)ceil(2.0 * tmax / dt);
+          if (p.ntb < 1) p.ntb = 1;
+          p.dt = dt;
+          p.tmin = -0.5 * dt * p.ntb;
+        }
+        finish_plan(g, rows_max, n, p);
+        const double items = nn / p.ev_per_wg + (nn < p.nbins ? nn : (double)p.nbins);
+        const double cost =
+            nn * pairs_per_event * (waves == 16 ? 1.1 : 1.0) + 1.6 * items * (double)pitch * (double)W;
+        if (!best.tiled || cost < best_cost) {
+          best = p;
+          best_cost = cost;
+        }
+      }
+    }
+  }
+  return best;
 }
 
 size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Workspace* out) {
@@ -260,15 +278,20 @@ size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Work
 // Every binned instance runs with the same wavefront count and register-cache length (those of
 // the most demanding instance) so that one kernel serves the whole batch; the table is sorted by
 // estimated work per workgroup, heaviest first, so that the longest workgroups start earliest.
-struct BatchLayout {
-  int waves = 8;
+struct BatchGroup {  // instances served by one launch (same accumulator width)
+  int first = 0, count = 0;  // table positions
   int maxlen = 16;
   size_t lds = 0;
+  int64_t grid = 0;
+};
+
+struct BatchLayout {
+  int waves = 8;
+  BatchGroup group[2];         // 64-bit, then 32-bit LDS accumulators
   std::vector<Plan> plan;      // per instance
   std::vector<size_t> off;     // per instance: byte offset of its workspace
   std::vector<int> order;      // table position -> instance
-  std::vector<int64_t> begin;  // per instance: first workgroup in the batched grid
-  int64_t grid = 0;
+  std::vector<int64_t> begin;  // per instance: first workgroup in its group's grid
   int64_t max_npix = 0;
   size_t total = 0;
 };
@@ -290,25 +313,32 @@ BatchLayout batch_layout(const jpet_instance* inst, int count) {
     Plan p = make_plan(&g, g.sigma_z, g.sigma_dl, inst[k].n, L.waves);
     L.plan[k] = p;
     if (p.tiled) {
-      if (p.maxlen > L.maxlen) L.maxlen = p.maxlen;
-      if (p.lds_bytes > L.lds) L.lds = p.lds_bytes;
+      BatchGroup& G = L.group[p.acc32 ? 1 : 0];
+      if (p.maxlen > G.maxlen) G.maxlen = p.maxlen;
+      if (p.lds_bytes > G.lds) G.lds = p.lds_bytes;
       // pixels of a typical ellipse (App. B half sizes at theta = 0) times events per workgroup
       work[k] = (1.5 * g.sigma_dl / g.pixel) * (3.0 * g.sigma_z / sqrt(2.0) / g.pixel) * p.ev_per_wg;
     }
     const int64_t np = npix_of(&g);
     if (np > L.max_npix) L.max_npix = np;
   }
+  auto rank = [&](int k) { return L.plan[k].tiled ? (L.plan[k].acc32 ? 1 : 0) : 2; };
   L.order.resize(count);
   for (int k = 0; k < count; ++k) L.order[k] = k;
-  // tiled first by decreasing work (stable: ties keep the caller's order), generic instances last
+  // groups in turn (generic instances last), each by decreasing work; ties keep the caller's order
   std::stable_sort(L.order.begin(), L.order.end(), [&](int a, int b) {
-    if (L.plan[a].tiled != L.plan[b].tiled) return L.plan[a].tiled > L.plan[b].tiled;
+    if (rank(a) != rank(b)) return rank(a) < rank(b);
     return work[a] > work[b];
   });
   for (int t = 0; t < count; ++t) {
     const int k = L.order[t];
-    L.begin[k] = L.grid;
-    if (L.plan[k].tiled) L.grid += L.plan[k].max_items;
+    const int r = rank(k);
+    if (r == 2) continue;
+    BatchGroup& G = L.group[r];
+    if (G.count == 0) G.first = t;
+    ++G.count;
+    L.begin[k] = G.grid;
+    G.grid += L.plan[k].max_items;
   }
   size_t off = align_up(sizeof(BatchInst) * (size_t)count, 256);
   for (int k = 0; k < count; ++k) {
@@ -449,6 +479,7 @@ int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_
   info->t_bin_width = p.ntb > 1 ? p.dt : 0.0;
   info->lds_bytes = (int64_t)p.lds_bytes;
   info->max_workgroups = p.max_items;
+  info->accumulator_bits = p.tiled ? (p.acc32 ? 32 : 64) : 64;
   return JPET_OK;
 }
 
@@ -541,9 +572,12 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
     mdl = sigma_mask[1];
     if (!finite_pos(msz) || !finite_pos(mdl)) return JPET_EDOMAIN;
   }
-  // the gradient pass walks events in input order and needs no binning
+  // a prepared workspace carries the kernel constants of the sigmas it was prepared with
+  if ((flags & JPET_WS_PREPARED) && (msz != g->sigma_z || mdl != g->sigma_dl)) return JPET_EINVAL;
   Plan p = make_plan(g, msz, mdl, n);
-  p.tiled = 0;
+  // the binned log-likelihood pass accumulates doubles (64-bit region slots); plans with 32-bit
+  // slots use the generic pass, which reads the per-event records every plan keeps
+  if (p.acc32) p.tiled = 0;
   Workspace w;
   rc = carve(p, g, n, ws, ws_bytes, &w);
   if (rc) return rc;
@@ -555,7 +589,7 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
   }
   hipError_t e = launch_fill_u64(w.cnt + C_ZERO_DEN, 2, st);
   if (e != hipSuccess) return hip_fail(e);
-  e = launch_loglik(geo, n, w, rho, s, D_out, grad_rho, out3, st);
+  e = launch_loglik(geo, p, n, w, rho, s, D_out, grad_rho, out3, st);
   if (e != hipSuccess) return hip_fail(e);
   if (stats) {
     rc = read_stats(w, n, stats, st);
@@ -647,7 +681,16 @@ int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t 
     if ((e = launch_fill_u64(w[k].acc, npix_of(&inst[k].g), st)) != hipSuccess) return hip_fail(e);
   for (int it = 0; it < n_iter; ++it) {
     if ((e = launch_batched_reset(table, count, st)) != hipSuccess) return hip_fail(e);
-    rc = timed([&] { return launch_event_pass_batched(table, count, L.maxlen, L.waves, L.lds, L.grid, st); }, st);
+    rc = timed(
+        [&] {
+          hipError_t r = hipSuccess;
+          for (int gi = 0; gi < 2 && r == hipSuccess; ++gi) {
+            const BatchGroup& G = L.group[gi];
+            r = launch_event_pass_batched(table + G.first, G.count, G.maxlen, L.waves, gi, G.lds, G.grid, st);
+          }
+          return r;
+        },
+        st);
     if (rc) return rc;
     for (int k = 0; k < count; ++k) {
       if (L.plan[k].tiled) continue;

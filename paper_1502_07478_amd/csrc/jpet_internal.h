@@ -39,7 +39,8 @@ struct EventRec {
 //   S q   = S bC^-1b         = S 2u b1^2 + Q3s dy^2            (S = log2(e) / 2)
 struct EvConst {
   float yr, zr;         // y~ and z~ relative to the centre of the bin region's pixel (0, 0)
-  int32_t pad0[2];
+  int32_t index;        // position of the event in the caller's array
+  int32_t pad0;
   float t;              // tan(theta~)
   float A1, A2, A3, KB; // 2u c^4, w fa^2 c^2 t^2, 4 w c^2 (1 + 2t^2), -4 u t c^2
   float G1, GB, Q3s;    // 2 fa w c^2 t, -2 u c^2, S 4 w c^2
@@ -77,6 +78,7 @@ struct Plan {
   double tmin, dt;      // t bin b spans [tmin + b dt, tmin + (b+1) dt); ntb == 1: no shear
   int maxlen;           // register cache length (16/32/48/64) >= longest ellipse row
   int waves;            // wavefronts per workgroup
+  int acc32;            // 1: 32-bit LDS accumulators in 2^-24 units (regions too large for 64-bit ones)
   int ev_per_batch;     // events whose rows are processed together (rows <= 64 * waves)
   int ev_per_wg;        // events per workgroup item (a multiple of ev_per_batch)
   int64_t max_items;    // upper bound of workgroup items (the launch grid)
@@ -164,10 +166,13 @@ hipError_t launch_update(const Geo& g, const float* s, float* rho, const Workspa
 // batched: table of count instances in device memory; grid = total workgroups of the tiled ones
 hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t st);
 hipError_t launch_batched_reset(const BatchInst* table, int count, hipStream_t st);
-hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxlen, int waves, size_t lds_bytes,
-                                     int64_t grid, hipStream_t st);
+hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxlen, int waves, int acc32,
+                                     size_t lds_bytes, int64_t grid, hipStream_t st);
 hipError_t launch_update_batched(const BatchInst* table, int count, int64_t max_npix, hipStream_t st);
-hipError_t launch_loglik(const Geo& g, int64_t n, const Workspace& ws, const float* rho, const float* s,
-                         float* D_out, float* grad_rho, double* out3, hipStream_t st);
+hipError_t launch_loglik(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
+                         const float* s, float* D_out, float* grad_rho, double* out3, hipStream_t st);
+// the binned log-likelihood pass (B and red[0..2] zeroed by the caller)
+hipError_t launch_loglik_tiled(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
+                               float* D_out, hipStream_t st);
 
 }  // namespace jpet

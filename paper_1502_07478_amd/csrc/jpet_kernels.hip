@@ -26,6 +26,11 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n) {
     p[i] = 0ull;
 }
 
+__global__ void k_fill_f32(float* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
 __global__ void k_fill_f64(double* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0.0;
@@ -228,14 +233,25 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_loglik(const Geo& g, int64_t n, const Workspace& ws, const float* rho, const float* s,
-                         float* D_out, float* grad_rho, double* out3, hipStream_t st) {
+hipError_t launch_loglik(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
+                         const float* s, float* D_out, float* grad_rho, double* out3, hipStream_t st) {
   const int64_t npix = (int64_t)g.n_y * g.n_z;
-  const int blocks = grid_for(n, 256 / WAVE, RED_SLOTS / 3);
-  if (grad_rho) hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(npix, 256)), dim3(256), 0, st, ws.B, npix);
-  hipLaunchKernelGGL(k_loglik_pass, dim3(blocks), dim3(256), 0, st, g, n, ws.ev, rho, grad_rho ? ws.B : nullptr,
-                     D_out, ws.red, ws.cnt);
-  hipLaunchKernelGGL(k_loglik_finish, dim3(1), dim3(256), 0, st, g, blocks, ws.red, rho, s, ws.cnt, out3);
+  int nparts;
+  if (p.tiled) {
+    // binned pass: B always accumulated (the pass has no B-free variant), three partial sums
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(npix, 256)), dim3(256), 0, st, ws.B, npix);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, ws.red, (int64_t)3);
+    if (D_out) hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256)), dim3(256), 0, st, D_out, n);
+    const hipError_t e = launch_loglik_tiled(g, p, n, ws, rho, D_out, st);
+    if (e != hipSuccess) return e;
+    nparts = 1;
+  } else {
+    nparts = grid_for(n, 256 / WAVE, RED_SLOTS / 3);
+    if (grad_rho) hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(npix, 256)), dim3(256), 0, st, ws.B, npix);
+    hipLaunchKernelGGL(k_loglik_pass, dim3(nparts), dim3(256), 0, st, g, n, ws.ev, rho, grad_rho ? ws.B : nullptr,
+                       D_out, ws.red, ws.cnt);
+  }
+  hipLaunchKernelGGL(k_loglik_finish, dim3(1), dim3(256), 0, st, g, nparts, ws.red, rho, s, ws.cnt, out3);
   if (grad_rho) hipLaunchKernelGGL(k_grad_rho, dim3(grid_for(npix, 256)), dim3(256), 0, st, npix, ws.B, s, grad_rho);
   return hipGetLastError();
 }

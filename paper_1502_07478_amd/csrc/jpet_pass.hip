@@ -12,6 +12,8 @@
 // and independent of the order in which events are processed.
 //
 // The constant factor u sqrt(w) / (2 pi) of Eq. 7 cancels in m / D and is not applied.
+#include <type_traits>
+
 #include "jpet_device.h"
 
 namespace jpet {
@@ -96,16 +98,96 @@ __device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __
 
 // Pass 2 along one row: m sc rounded into the 64-bit accumulators.  Below wmin every lane adds
 // (idle lanes and lanes with D = 0 add 0 at a valid address); above it the row end masks.
-template <int MAXLEN, bool PRESCALE>
+template <int MAXLEN, bool PRESCALE, typename AccT>
 __device__ __forceinline__ void pass2(const float (&m)[MAXLEN], float sc, int base, int pitch, int len, int wmin,
-                                      int wl, unsigned long long* __restrict__ acc_s) {
+                                      int wl, AccT* __restrict__ acc_s) {
 #pragma unroll
   for (int j = 0; j < MAXLEN; ++j) {
     const float x = PRESCALE ? m[j] * 18446744073709551616.0f : m[j];
     if (j < wmin) {  // wavefront-uniform
-      atomicAdd(&acc_s[base + j * pitch], (unsigned long long)(unsigned)fmaf(x, sc, 0.5f));
+      atomicAdd(&acc_s[base + j * pitch], (AccT)(unsigned)fmaf(x, sc, 0.5f));
     } else if (j < wl && j < len) {
-      atomicAdd(&acc_s[base + j * pitch], (unsigned long long)(unsigned)fmaf(x, sc, 0.5f));
+      atomicAdd(&acc_s[base + j * pitch], (AccT)(unsigned)fmaf(x, sc, 0.5f));
+    }
+  }
+}
+
+// Log-likelihood mode.  Per pixel, besides P' (the kernel without its constant factor), the
+// derivatives of log P with respect to u = sigma_z^-2 and w = sigma_dl^-2 (gamma = 0), written with
+// kappa = u Kz + w Kl, gamma = u Gz + w Gl, q = u Bz + w Bl, Bz = 2 b1^2, g = gamma / kappa and
+// h = 1/kappa + g^2:
+//   dlogP/du = 1/u - b1^2 + g Gz - Kz h / 2,    dlogP/dw = 1/(2w) - Bl/2 + g Gl - Kl h / 2.
+// Along a row Kz and Gz are affine in the pixel offset j; Kl, Gl, Bl are constant.
+struct RowD {
+  float b10, Kzh0, dKzh, Gz0, dGz, Gl, Klh, cw;  // Kzh = Kz / 2, Klh = Kl / 2, cw = 1/(2w) - Bl/2
+};
+
+struct GradShared {
+  float Du[3][kMaxBatch];  // per-event sums of rho P' dlogP/du, buffered like D
+  float Dw[3][kMaxBatch];
+};
+
+template <int MAXLEN, bool GUARD>
+__device__ __forceinline__ void pass1g(const RowF& rk, const RowD& rd, float qa, float pixf, float cu, float irs,
+                                       const float* __restrict__ rho_s, int base, int pitch, int len, int wmin,
+                                       int wl, float (&m)[MAXLEN], bool* bad, float& D, float& Du, float& Dw) {
+  D = 0.0f;
+  Du = 0.0f;
+  Dw = 0.0f;
+#pragma unroll
+  for (int j0 = 0; j0 < MAXLEN; j0 += kChunk) {
+    if (j0 < wl) {  // wavefront-uniform
+      float r[kChunk];
+#pragma unroll
+      for (int jj = 0; jj < kChunk; ++jj) r[jj] = rho_s[base + (j0 + jj) * pitch];
+      const bool full = !GUARD && j0 + kChunk <= wmin;  // wavefront-uniform
+#pragma unroll
+      for (int jj = 0; jj < kChunk; ++jj) {
+        const int j = j0 + jj;
+        const float jf = (float)j;
+        float kap = fmaf(jf, rk.dkap, rk.kap0);
+        bool keep = full || j < len;
+        if (GUARD && !(kap > 0.0f)) {
+          if (keep) *bad = true;
+          keep = false;
+          kap = 1.0f;
+        }
+        const float gs = fmaf(jf, rk.dgs, rk.gs0);
+        const float rq = __builtin_amdgcn_rsqf(kap);
+        const float sq = fmaf(fmaf(qa, jf, rk.qb), jf, rk.qc);
+        const float tg = gs * rq;
+        const float pv = rq * __builtin_amdgcn_exp2f(fmaf(tg, tg, -sq));
+        const float b1 = fmaf(jf, pixf, rd.b10);
+        const float Kzh = fmaf(jf, rd.dKzh, rd.Kzh0);
+        const float Gz = fmaf(jf, rd.dGz, rd.Gz0);
+        const float gk = tg * rq * irs;
+        const float h = fmaf(gk, gk, rq * rq);
+        const float du = fmaf(-Kzh, h, fmaf(gk, Gz, fmaf(-b1, b1, cu)));
+        const float dw = fmaf(-rd.Klh, h, fmaf(gk, rd.Gl, rd.cw));
+        const float pk = keep ? pv : 0.0f;
+        const float v = pk * r[jj];
+        m[j] = pk;
+        D += v;
+        Du = fmaf(v, du, Du);
+        Dw = fmaf(v, dw, Dw);
+      }
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < kChunk; ++jj) m[j0 + jj] = 0.0f;
+    }
+  }
+}
+
+// B += P' / D' (= P / D) into the region's double accumulators.
+template <int MAXLEN>
+__device__ __forceinline__ void pass2g(const float (&m)[MAXLEN], float invD, int base, int pitch, int len, int wmin,
+                                       int wl, double* __restrict__ B_s) {
+#pragma unroll
+  for (int j = 0; j < MAXLEN; ++j) {
+    if (j < wmin) {  // wavefront-uniform
+      unsafeAtomicAdd(&B_s[base + j * pitch], (double)(m[j] * invD));
+    } else if (j < wl && j < len) {
+      unsafeAtomicAdd(&B_s[base + j * pitch], (double)(m[j] * invD));
     }
   }
 }
@@ -128,18 +210,26 @@ __device__ __forceinline__ void copy_consts(const unsigned char* __restrict__ sr
 // wavefront holds rows of nearly equal length, consecutive within each half-wavefront), so the
 // pixel at column offset j of every lane's row falls into a different bank whatever the slant of
 // the ellipse.
-template <int MAXLEN, int WAVES>
+// One workgroup item.  GRAD = false: the MLEM event pass (acc: 2^-32 fixed-point image; the LDS
+// accumulators are 64-bit in 2^-32 units, or with ACC32 32-bit in 2^-24 units).
+// GRAD = true: the log-likelihood pass (acc: double image B = sum P / D; per-event log D' and the
+// sigma-derivative sums into red[0..2]; D' times the kernel's constant factor into D_out).
+template <int MAXLEN, int WAVES, bool GRAD, bool ACC32>
 __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, const unsigned char* __restrict__ blocks,
                                                 const BinItem it, const float* __restrict__ rho,
                                                 unsigned long long* __restrict__ acc,
                                                 unsigned long long* __restrict__ cnt, unsigned char* smem,
-                                                PassShared& ps) {
+                                                PassShared& ps, GradShared* gsh, float* __restrict__ D_out,
+                                                double* __restrict__ red) {
   const int pitch = p.pitch;  // rows of a column in LDS
   const int npx = pitch * p.W;
   // the image first, then the accumulators: reads past the end of a row (masked lanes) land in
   // the accumulator array, which is larger than MAXLEN columns of the image
   float* rho_s = reinterpret_cast<float*>(smem);
-  unsigned long long* acc_s = reinterpret_cast<unsigned long long*>(smem + (size_t)npx * sizeof(float));
+  static_assert(!(GRAD && ACC32), "the log-likelihood pass accumulates doubles");
+  using AccT = typename std::conditional<ACC32, unsigned, unsigned long long>::type;
+  AccT* acc_s = reinterpret_cast<AccT*>(smem + (size_t)npx * sizeof(float));
+  constexpr float kUnit = ACC32 ? 16777216.0f : 4294967296.0f;  // accumulator units per count
 
   const int tz = it.bin % p.ntz;
   const int rest = it.bin / p.ntz;
@@ -172,7 +262,20 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
     ps.D[0][tid] = 0.0;
     ps.D[1][tid] = 0.0;
     ps.D[2][tid] = 0.0;
+    if constexpr (GRAD) {
+      for (int b = 0; b < 3; ++b) {
+        gsh->Du[b][tid] = 0.0f;
+        gsh->Dw[b][tid] = 0.0f;
+      }
+    }
   }
+  // log-likelihood mode: per-thread double sums of log D', Du / D', Dw / D' (events tid < 32)
+  double s_log = 0.0, s_du = 0.0, s_dw = 0.0;
+  int pidx = -1;  // input index of event tid of the previous batch
+  const float iu = (float)(1.0 / g.u), iw = (float)(1.0 / g.w);
+  const float irs = 1.1774100225154747f;     // 1 / sqrt(log2(e) / 2)
+  const float iS = 1.3862943611198906f;      // 1 / (log2(e) / 2)
+  const float Dnorm = (float)(g.u * sqrt(g.w) / (2.0 * kPi));
   if (tid == 0) {
     ps.zero = 0u;
     ps.bad = 0u;
@@ -192,7 +295,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
         if (k >= 0 && k < g.n_z) v = rho[(int64_t)r * g.n_z + k];
       }
       rho_s[q] = v;
-      acc_s[q] = 0ull;
+      acc_s[q] = 0;
     }
   }
   __builtin_amdgcn_s_waitcnt(0);
@@ -205,24 +308,43 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   int plen = 0, pbase = 0, pe = 0, pwl = 0, pwn = 0;  // the row held in m (previous batch)
   const float Yb = (float)(g.y0 + (double)rbase * g.pixel);  // y of the region's first row
   for (int bi = 0; bi <= nbatch; ++bi) {
-    // pass 2 of batch bi - 1: m / D into the region accumulators (2^-32 fixed point)
+    // pass 2 of batch bi - 1: m / D into the region accumulators (2^-32 fixed point), or in the
+    // log-likelihood mode P / D into B and the per-event terms
     if (bi > 0) {
       const double* Dp = ps.D[(bi - 1) % 3];
       const double Dd = plen > 0 ? Dp[pe] : 1.0;
       const int n2 = Dd > 0.0 ? plen : 0;
-      // 2^32 / D overflows a float only for D < 1.3e-29; such wavefronts pre-scale m by 2^64
-      if (__any(n2 > 0 && Dd < 1e-28)) {
-        const float sc = n2 > 0 ? (float)(4294967296.0 / (Dd * 18446744073709551616.0)) : 0.0f;
-        pass2<MAXLEN, true>(m, sc, pbase, pitch, n2, pwn, pwl, acc_s);
+      if constexpr (GRAD) {
+        const float invD = n2 > 0 ? (float)(1.0 / Dd) : 0.0f;
+        pass2g<MAXLEN>(m, invD, pbase, pitch, n2, pwn, pwl, reinterpret_cast<double*>(acc_s));
+        const int nbp = min(p.ev_per_batch, it.count - (bi - 1) * p.ev_per_batch);
+        if (tid < nbp) {
+          const double De = Dp[tid];
+          if (De > 0.0) {
+            s_log += log(De);
+            s_du += (double)gsh->Du[(bi - 1) % 3][tid] / De;
+            s_dw += (double)gsh->Dw[(bi - 1) % 3][tid] / De;
+          } else {
+            atomicAdd(&ps.zero, 1u);
+          }
+          if (D_out) D_out[pidx] = (float)(De > 0.0 ? De * (double)Dnorm : 0.0);
+        }
       } else {
-        const float sc = n2 > 0 ? 4294967296.0f * __builtin_amdgcn_rcpf((float)Dd) : 0.0f;
-        pass2<MAXLEN, false>(m, sc, pbase, pitch, n2, pwn, pwl, acc_s);
+        // 2^32 / D overflows a float only for D < 1.3e-29; such wavefronts pre-scale m by 2^64
+        if (__any(n2 > 0 && Dd < 1e-28)) {
+          const float sc = n2 > 0 ? (float)((double)kUnit / (Dd * 18446744073709551616.0)) : 0.0f;
+          pass2<MAXLEN, true>(m, sc, pbase, pitch, n2, pwn, pwl, acc_s);
+        } else {
+          const float sc = n2 > 0 ? kUnit * __builtin_amdgcn_rcpf((float)Dd) : 0.0f;
+          pass2<MAXLEN, false>(m, sc, pbase, pitch, n2, pwn, pwl, acc_s);
+        }
+        const int nbp = min(p.ev_per_batch, it.count - (bi - 1) * p.ev_per_batch);
+        if (tid < nbp && !(Dp[tid] > 0.0)) atomicAdd(&ps.zero, 1u);
       }
-      const int nbp = min(p.ev_per_batch, it.count - (bi - 1) * p.ev_per_batch);
-      if (tid < nbp && !(Dp[tid] > 0.0)) atomicAdd(&ps.zero, 1u);
     }
     if (bi < nbatch) {
       const int buf = bi & 1;
+      const int nb = min(p.ev_per_batch, it.count - bi * p.ev_per_batch);
       // prefetch the next batch: constants into the other LDS buffer, this thread's next word
       uint32_t next = 0u;
       int wl_next = 0, wn_next = 0;
@@ -240,6 +362,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       int base = 0;
       bool safe = true;
       RowF rk = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 1e30f};  // idle lane: every kernel value is 0
+      RowD rd = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       if (len > 0) {
         const int kl = (int)((word >> kWordCol) & 255u);
         const int rl = (int)((word >> kWordRow) & 511u);
@@ -258,18 +381,36 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
         rk.dgs = rs * gb * pixf;
         rk.qb = 2.0f * S2u * b10 * pixf;
         rk.qc = fmaf(S2u * b10, b10, c.Q3s * dy * dy);
+        if constexpr (GRAD) {
+          rd.b10 = b10;
+          rd.Kzh0 = 0.5f * iu * fmaf(kb, b10, c.A1 * (R2 + Y * Y));
+          rd.dKzh = 0.5f * iu * kb * pixf;
+          rd.Gz0 = iu * gb * b10;
+          rd.dGz = iu * gb * pixf;
+          rd.Gl = iw * c.G1 * Y * dy;
+          rd.Klh = 0.5f * iw * Y * fmaf(c.A2, Y, c.A3 * dy);
+          rd.cw = 0.5f * iw * (1.0f - iS * c.Q3s * dy * dy);
+        }
         const float kend = fmaf((float)(len - 1), rk.dkap, rk.kap0);
         safe = rk.kap0 > 1e-3f * fabsf(rk.kap0) && kend > 1e-3f * fabsf(rk.kap0);
         base = kl * pitch + rl;
       }
 
-      // pass 1: m = P rho along the row, D partial sums
+      // pass 1: m = P rho along the row (log-likelihood mode: m = P), D partial sums
       bool bad = false;
-      float D;
-      if (__any(!safe)) {
-        D = pass1<MAXLEN, true>(rk, qa, rho_s, base, pitch, len, wn, wl, m, &bad);
+      float D, Du = 0.0f, Dw = 0.0f;
+      if constexpr (GRAD) {
+        if (__any(!safe)) {
+          pass1g<MAXLEN, true>(rk, rd, qa, pixf, iu, irs, rho_s, base, pitch, len, wn, wl, m, &bad, D, Du, Dw);
+        } else {
+          pass1g<MAXLEN, false>(rk, rd, qa, pixf, iu, irs, rho_s, base, pitch, len, wn, wl, m, &bad, D, Du, Dw);
+        }
       } else {
-        D = pass1<MAXLEN, false>(rk, qa, rho_s, base, pitch, len, wn, wl, m, &bad);
+        if (__any(!safe)) {
+          D = pass1<MAXLEN, true>(rk, qa, rho_s, base, pitch, len, wn, wl, m, &bad);
+        } else {
+          D = pass1<MAXLEN, false>(rk, qa, rho_s, base, pitch, len, wn, wl, m, &bad);
+        }
       }
       if (bad) atomicAdd(&ps.bad, 1u);
 
@@ -282,11 +423,26 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
         const bool mine = len > 0 && e == el;
         const float v = wave_sum_dpp(mine ? D : 0.0f);
         if (lane == 0) atomicAdd(&Dc[el], (double)v);
+        if constexpr (GRAD) {
+          const float vu = wave_sum_dpp(mine ? Du : 0.0f);
+          const float vw = wave_sum_dpp(mine ? Dw : 0.0f);
+          if (lane == 0) {
+            atomicAdd(&gsh->Du[bi % 3][el], vu);
+            atomicAdd(&gsh->Dw[bi % 3][el], vw);
+          }
+        }
         act &= ~__ballot(mine);
       }
       // batch bi + 1 accumulates into D[(bi + 1) % 3], last read (as batch bi - 2's) before the
       // previous barrier
-      if (tid < kMaxBatch) ps.D[(bi + 1) % 3][tid] = 0.0;
+      if (tid < kMaxBatch) {
+        ps.D[(bi + 1) % 3][tid] = 0.0;
+        if constexpr (GRAD) {
+          gsh->Du[(bi + 1) % 3][tid] = 0.0f;
+          gsh->Dw[(bi + 1) % 3][tid] = 0.0f;
+        }
+      }
+      if constexpr (GRAD) pidx = tid < nb ? ps.ev[buf][tid].index : -1;
       plen = len;
       pbase = base;
       pe = e;
@@ -304,11 +460,27 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   for (int cl = wave; cl < p.W; cl += WAVES) {
     const int kc = kbase + cl;
     for (int rl = lane; rl < p.RY; rl += WAVE) {
-      const unsigned long long a = acc_s[cl * pitch + rl];
+      const unsigned long long a = (unsigned long long)acc_s[cl * pitch + rl] << (ACC32 ? 8 : 0);
       if (a == 0ull) continue;
       const int r = rbase + rl;
       const int k = kc + ps.off[rl];
-      if (r >= 0 && r < g.n_y && k >= 0 && k < g.n_z) atomicAdd(&acc[(int64_t)r * g.n_z + k], a);
+      if (r >= 0 && r < g.n_y && k >= 0 && k < g.n_z) {
+        if constexpr (GRAD) {
+          unsafeAtomicAdd(reinterpret_cast<double*>(acc) + (int64_t)r * g.n_z + k, __longlong_as_double((long long)a));
+        } else {
+          atomicAdd(&acc[(int64_t)r * g.n_z + k], a);
+        }
+      }
+    }
+  }
+  if constexpr (GRAD) {  // events of the first wavefront only carry sums
+    if (tid < WAVE) {
+      const double a = wave_sum_d(s_log), b = wave_sum_d(s_du), c = wave_sum_d(s_dw);
+      if (tid == 0) {
+        unsafeAtomicAdd(&red[0], a);
+        unsafeAtomicAdd(&red[1], b);
+        unsafeAtomicAdd(&red[2], c);
+      }
     }
   }
   if (tid == 0) {
@@ -317,7 +489,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   }
 }
 
-template <int MAXLEN, int WAVES>
+template <int MAXLEN, int WAVES, bool ACC32>
 __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan p,
                                                                     const unsigned char* __restrict__ blocks,
                                                                     const BinItem* __restrict__ items,
@@ -327,13 +499,30 @@ __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan 
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ PassShared ps;
   if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
-  event_pass_item<MAXLEN, WAVES>(g, p, blocks, items[blockIdx.x], rho, acc, cnt, smem, ps);
+  event_pass_item<MAXLEN, WAVES, false, ACC32>(g, p, blocks, items[blockIdx.x], rho, acc, cnt, smem, ps, nullptr,
+                                              nullptr, nullptr);
+}
+
+// The log-likelihood pass on the binned layout (B: double image of sum P / D, zeroed by the
+// caller; red[0..2]: log D', Du / D', Dw / D' sums, zeroed by the caller).
+template <int MAXLEN, int WAVES>
+__global__ void __launch_bounds__(WAVES * 64, 4) k_loglik_tiled(Geo g, Plan p, const unsigned char* __restrict__ blocks,
+                                                                const BinItem* __restrict__ items,
+                                                                const float* __restrict__ rho, double* __restrict__ B,
+                                                                float* __restrict__ D_out, double* __restrict__ red,
+                                                                unsigned long long* __restrict__ cnt) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ PassShared ps;
+  __shared__ GradShared gsh;
+  if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
+  event_pass_item<MAXLEN, WAVES, true, false>(g, p, blocks, items[blockIdx.x], rho,
+                                             reinterpret_cast<unsigned long long*>(B), cnt, smem, ps, &gsh, D_out, red);
 }
 
 // The same pass over many independent reconstructions in one launch: the grid is the
 // concatenation of the instances' work lists (table sorted by item_begin); each workgroup finds
 // its instance by binary search.
-template <int MAXLEN, int WAVES>
+template <int MAXLEN, int WAVES, bool ACC32>
 __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_batched(const BatchInst* __restrict__ inst,
                                                                       int count) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -348,7 +537,8 @@ __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_batched(const Batc
   const BatchInst& I = inst[lo];
   const int64_t local = b - I.item_begin;
   if (!I.tiled || local >= (int64_t)I.cnt[C_ITEMS]) return;
-  event_pass_item<MAXLEN, WAVES>(I.g, I.p, I.blocks, I.items[local], I.rho, I.acc, I.cnt, smem, ps);
+  event_pass_item<MAXLEN, WAVES, false, ACC32>(I.g, I.p, I.blocks, I.items[local], I.rho, I.acc, I.cnt, smem, ps,
+                                              nullptr, nullptr, nullptr);
 }
 
 // Generic pass for geometries whose rows or regions do not fit the tiled pass: one wavefront per
@@ -415,9 +605,9 @@ __global__ void k_update(int64_t npix, const float* __restrict__ s, float* __res
   }
 }
 
-template <int MAXLEN, int WAVES>
+template <int MAXLEN, int WAVES, bool ACC32>
 hipError_t launch_tiled(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, hipStream_t st) {
-  auto kern = k_event_pass_tiled<MAXLEN, WAVES>;
+  auto kern = k_event_pass_tiled<MAXLEN, WAVES, ACC32>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)p.max_items), dim3(64 * p.waves), p.lds_bytes, st, g, p, ws.batches,
@@ -425,9 +615,9 @@ hipError_t launch_tiled(const Geo& g, const Plan& p, const Workspace& ws, const 
   return hipGetLastError();
 }
 
-template <int MAXLEN, int WAVES>
+template <int MAXLEN, int WAVES, bool ACC32>
 hipError_t launch_batched(const BatchInst* table, int count, size_t lds_bytes, int64_t grid, hipStream_t st) {
-  auto kern = k_event_pass_batched<MAXLEN, WAVES>;
+  auto kern = k_event_pass_batched<MAXLEN, WAVES, ACC32>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * WAVES), lds_bytes, st, table, count);
@@ -465,7 +655,34 @@ __global__ void k_update_batched(const BatchInst* __restrict__ table) {
   }
 }
 
+template <int MAXLEN, int WAVES>
+hipError_t launch_loglik_t(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, float* D_out,
+                           hipStream_t st) {
+  auto kern = k_loglik_tiled<MAXLEN, WAVES>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)p.max_items), dim3(64 * p.waves), p.lds_bytes, st, g, p, ws.batches,
+                     ws.items, rho, ws.B, D_out, ws.red, ws.cnt);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_loglik_tiled(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
+                               float* D_out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  switch (p.maxlen * 100 + p.waves) {
+    case 1608: return launch_loglik_t<16, 8>(g, p, ws, rho, D_out, st);
+    case 3208: return launch_loglik_t<32, 8>(g, p, ws, rho, D_out, st);
+    case 4808: return launch_loglik_t<48, 8>(g, p, ws, rho, D_out, st);
+    case 6408: return launch_loglik_t<64, 8>(g, p, ws, rho, D_out, st);
+    case 1616: return launch_loglik_t<16, 16>(g, p, ws, rho, D_out, st);
+    case 3216: return launch_loglik_t<32, 16>(g, p, ws, rho, D_out, st);
+    case 4816: return launch_loglik_t<48, 16>(g, p, ws, rho, D_out, st);
+    case 6416: return launch_loglik_t<64, 16>(g, p, ws, rho, D_out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t st) {
   hipLaunchKernelGGL(k_write_insts, dim3(1), dim3(64), 0, st, w, table);
@@ -478,18 +695,22 @@ hipError_t launch_batched_reset(const BatchInst* table, int count, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxlen, int waves, size_t lds_bytes,
-                                     int64_t grid, hipStream_t st) {
+hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxlen, int waves, int acc32,
+                                     size_t lds_bytes, int64_t grid, hipStream_t st) {
   if (count <= 0 || grid <= 0) return hipSuccess;
-  switch (maxlen * 100 + waves) {
-    case 1608: return launch_batched<16, 8>(table, count, lds_bytes, grid, st);
-    case 3208: return launch_batched<32, 8>(table, count, lds_bytes, grid, st);
-    case 4808: return launch_batched<48, 8>(table, count, lds_bytes, grid, st);
-    case 6408: return launch_batched<64, 8>(table, count, lds_bytes, grid, st);
-    case 1616: return launch_batched<16, 16>(table, count, lds_bytes, grid, st);
-    case 3216: return launch_batched<32, 16>(table, count, lds_bytes, grid, st);
-    case 4816: return launch_batched<48, 16>(table, count, lds_bytes, grid, st);
-    case 6416: return launch_batched<64, 16>(table, count, lds_bytes, grid, st);
+  switch (maxlen * 100 + waves + (acc32 ? 10000 : 0)) {
+    case 1608: return launch_batched<16, 8, false>(table, count, lds_bytes, grid, st);
+    case 3208: return launch_batched<32, 8, false>(table, count, lds_bytes, grid, st);
+    case 4808: return launch_batched<48, 8, false>(table, count, lds_bytes, grid, st);
+    case 6408: return launch_batched<64, 8, false>(table, count, lds_bytes, grid, st);
+    case 1616: return launch_batched<16, 16, false>(table, count, lds_bytes, grid, st);
+    case 3216: return launch_batched<32, 16, false>(table, count, lds_bytes, grid, st);
+    case 4816: return launch_batched<48, 16, false>(table, count, lds_bytes, grid, st);
+    case 6416: return launch_batched<64, 16, false>(table, count, lds_bytes, grid, st);
+    case 11616: return launch_batched<16, 16, true>(table, count, lds_bytes, grid, st);
+    case 13216: return launch_batched<32, 16, true>(table, count, lds_bytes, grid, st);
+    case 14816: return launch_batched<48, 16, true>(table, count, lds_bytes, grid, st);
+    case 16416: return launch_batched<64, 16, true>(table, count, lds_bytes, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -506,16 +727,20 @@ hipError_t launch_event_pass(const Geo& g, const Plan& p, int64_t n, const Works
                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (p.tiled) {
-    const int key = p.maxlen * 100 + p.waves;
+    const int key = p.maxlen * 100 + p.waves + (p.acc32 ? 10000 : 0);
     switch (key) {
-      case 1608: return launch_tiled<16, 8>(g, p, ws, rho, st);
-      case 3208: return launch_tiled<32, 8>(g, p, ws, rho, st);
-      case 4808: return launch_tiled<48, 8>(g, p, ws, rho, st);
-      case 6408: return launch_tiled<64, 8>(g, p, ws, rho, st);
-      case 1616: return launch_tiled<16, 16>(g, p, ws, rho, st);
-      case 3216: return launch_tiled<32, 16>(g, p, ws, rho, st);
-      case 4816: return launch_tiled<48, 16>(g, p, ws, rho, st);
-      case 6416: return launch_tiled<64, 16>(g, p, ws, rho, st);
+      case 1608: return launch_tiled<16, 8, false>(g, p, ws, rho, st);
+      case 3208: return launch_tiled<32, 8, false>(g, p, ws, rho, st);
+      case 4808: return launch_tiled<48, 8, false>(g, p, ws, rho, st);
+      case 6408: return launch_tiled<64, 8, false>(g, p, ws, rho, st);
+      case 1616: return launch_tiled<16, 16, false>(g, p, ws, rho, st);
+      case 3216: return launch_tiled<32, 16, false>(g, p, ws, rho, st);
+      case 4816: return launch_tiled<48, 16, false>(g, p, ws, rho, st);
+      case 6416: return launch_tiled<64, 16, false>(g, p, ws, rho, st);
+      case 11616: return launch_tiled<16, 16, true>(g, p, ws, rho, st);
+      case 13216: return launch_tiled<32, 16, true>(g, p, ws, rho, st);
+      case 14816: return launch_tiled<48, 16, true>(g, p, ws, rho, st);
+      case 16416: return launch_tiled<64, 16, true>(g, p, ws, rho, st);
       default: return hipErrorInvalidValue;
     }
   }

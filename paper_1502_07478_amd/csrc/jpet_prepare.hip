@@ -240,7 +240,8 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
       EvConst k;
       k.yr = (float)(e.y - (g.y0 + (double)rbase * g.pixel));
       k.zr = (float)(e.z - (g.z0 + (double)kbase * g.pixel));
-      k.pad0[0] = k.pad0[1] = 0;
+      k.index = e.index;
+      k.pad0 = 0;
       k.t = t;
       k.A1 = 2.0f * u * c2 * c2;
       k.A2 = w * fa * fa * c2 * t * t;

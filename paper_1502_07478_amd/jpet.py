@@ -56,11 +56,11 @@ class Stats(ctypes.Structure):
 class LaunchInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "binned", "tile_rows", "tile_cols", "halo_rows", "halo_cols", "t_bins", "bins", "waves", "row_cache",
-        "events_per_batch", "events_per_workgroup", "reserved")] + [
+        "events_per_batch", "events_per_workgroup", "accumulator_bits")] + [
         ("t_bin_width", ctypes.c_double), ("lds_bytes", ctypes.c_int64), ("max_workgroups", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Instance(ctypes.Structure):
@@ -370,7 +370,10 @@ def loglik_grad(g: Geometry, events: torch.Tensor, rho: torch.Tensor, s: torch.T
         _need(s, "s", torch.float32, g.shape)
     n = events.shape[0]
     if ws is None:
-        ws = workspace(g, n, rho.device)
+        # the workspace layout follows the ellipse mask's sigmas
+        gm = g if sigma_mask is None else Geometry(g.R, g.L, float(sigma_mask[0]), float(sigma_mask[1]), g.gamma,
+                                                    g.pixel, g.n_y, g.n_z, g.kernel_variant, 0)
+        ws = workspace(gm, n, rho.device)
         prepared = False
     out3 = torch.zeros(3, dtype=torch.float64, device=rho.device)
     gr = torch.empty(g.shape, dtype=torch.float32, device=rho.device) if want_grad_rho else None

@@ -176,12 +176,29 @@ def test_events_at_grid_and_strip_edges(tiny):
 
 
 def test_long_rows_and_many_rows():
-    """sigma large against the pixel: rows longer than a wavefront and more than 64 rows per event."""
+    """sigma large against the pixel: more than 200 rows per event and a region that fits the LDS
+    only with 32-bit accumulators."""
     from jpet_synth import Workload
     w = Workload("wide", 450.0, 500.0, 15.0, 90.0, 1.171875, 512, 512, 3000, 1, 7, "c1")
     g, go = geoms(w)
+    info = jpet.launch_info(g, w.n_events)
+    assert info["binned"] == 1 and info["accumulator_bits"] == 32
     ev_np = w.events()
     got, want, st, sto = run_both(g, go, ev_np, np.ones((512, 512)))
+    assert st["n_pairs"] == sto["n_pairs"]
+    assert st["n_unplaced_rows"] == 0
+    assert rel_l2(got, want) <= 1e-4
+
+
+def test_rows_longer_than_the_register_cache_use_the_generic_pass():
+    """Rows of more than 64 pixels (sigma_z = 12 mm on 0.5 mm pixels): the one-wavefront-per-event
+    pass with global accumulation."""
+    from jpet_synth import Workload
+    w = Workload("fine", 450.0, 500.0, 12.0, 40.0, 0.5, 256, 256, 1500, 1, 11, "c1")
+    g, go = geoms(w)
+    assert jpet.launch_info(g, w.n_events)["binned"] == 0
+    ev_np = w.events()
+    got, want, st, sto = run_both(g, go, ev_np, np.ones((256, 256)))
     assert st["n_pairs"] == sto["n_pairs"]
     assert rel_l2(got, want) <= 1e-4
 
