@@ -214,14 +214,16 @@ __device__ __forceinline__ void copy_consts(const unsigned char* __restrict__ sr
 // accumulators are 64-bit in 2^-32 units, or with ACC32 32-bit in 2^-24 units).
 // GRAD = true: the log-likelihood pass (acc: double image B = sum P / D; per-event log D' and the
 // sigma-derivative sums into red[0..2]; D' times the kernel's constant factor into D_out).
-template <int MAXLEN, int WAVES, bool GRAD, bool ACC32>
+template <int MAXLEN, int WAVES, bool GRAD, bool ACC32, int PITCH>
 __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, const unsigned char* __restrict__ blocks,
                                                 const BinItem it, const float* __restrict__ rho,
                                                 unsigned long long* __restrict__ acc,
                                                 unsigned long long* __restrict__ cnt, unsigned char* smem,
                                                 PassShared& ps, GradShared* gsh, float* __restrict__ D_out,
                                                 double* __restrict__ red) {
-  const int pitch = p.pitch;  // rows of a column in LDS
+  // rows of a column in LDS; a compile-time pitch turns the per-pixel LDS addresses into
+  // immediate offsets
+  const int pitch = PITCH ? PITCH : p.pitch;
   const int npx = pitch * p.W;
   // the image first, then the accumulators: reads past the end of a row (masked lanes) land in
   // the accumulator array, which is larger than MAXLEN columns of the image
@@ -489,7 +491,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   }
 }
 
-template <int MAXLEN, int WAVES, bool ACC32>
+template <int MAXLEN, int WAVES, bool ACC32, int PITCH>
 __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan p,
                                                                     const unsigned char* __restrict__ blocks,
                                                                     const BinItem* __restrict__ items,
@@ -499,8 +501,8 @@ __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan 
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ PassShared ps;
   if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
-  event_pass_item<MAXLEN, WAVES, false, ACC32>(g, p, blocks, items[blockIdx.x], rho, acc, cnt, smem, ps, nullptr,
-                                              nullptr, nullptr);
+  event_pass_item<MAXLEN, WAVES, false, ACC32, PITCH>(g, p, blocks, items[blockIdx.x], rho, acc, cnt, smem, ps,
+                                                     nullptr, nullptr, nullptr);
 }
 
 // The log-likelihood pass on the binned layout (B: double image of sum P / D, zeroed by the
@@ -515,8 +517,9 @@ __global__ void __launch_bounds__(WAVES * 64, 4) k_loglik_tiled(Geo g, Plan p, c
   __shared__ PassShared ps;
   __shared__ GradShared gsh;
   if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
-  event_pass_item<MAXLEN, WAVES, true, false>(g, p, blocks, items[blockIdx.x], rho,
-                                             reinterpret_cast<unsigned long long*>(B), cnt, smem, ps, &gsh, D_out, red);
+  event_pass_item<MAXLEN, WAVES, true, false, 0>(g, p, blocks, items[blockIdx.x], rho,
+                                                reinterpret_cast<unsigned long long*>(B), cnt, smem, ps, &gsh, D_out,
+                                                red);
 }
 
 // The same pass over many independent reconstructions in one launch: the grid is the
@@ -537,8 +540,8 @@ __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_batched(const Batc
   const BatchInst& I = inst[lo];
   const int64_t local = b - I.item_begin;
   if (!I.tiled || local >= (int64_t)I.cnt[C_ITEMS]) return;
-  event_pass_item<MAXLEN, WAVES, false, ACC32>(I.g, I.p, I.blocks, I.items[local], I.rho, I.acc, I.cnt, smem, ps,
-                                              nullptr, nullptr, nullptr);
+  event_pass_item<MAXLEN, WAVES, false, ACC32, 0>(I.g, I.p, I.blocks, I.items[local], I.rho, I.acc, I.cnt, smem, ps,
+                                                 nullptr, nullptr, nullptr);
 }
 
 // Generic pass for geometries whose rows or regions do not fit the tiled pass: one wavefront per
@@ -607,7 +610,9 @@ __global__ void k_update(int64_t npix, const float* __restrict__ s, float* __res
 
 template <int MAXLEN, int WAVES, bool ACC32>
 hipError_t launch_tiled(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, hipStream_t st) {
-  auto kern = k_event_pass_tiled<MAXLEN, WAVES, ACC32>;
+  auto kern = p.pitch == 128   ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 128>
+              : p.pitch == 256 ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 256>
+                               : k_event_pass_tiled<MAXLEN, WAVES, ACC32, 0>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)p.max_items), dim3(64 * p.waves), p.lds_bytes, st, g, p, ws.batches,
