@@ -116,10 +116,9 @@ int jpet_abi_version(void);
  *   s_out: device float [n_y * n_z], written entirely. */
 int jpet_sensitivity(const jpet_geometry* g, float* s_out, void* stream);
 
-/* Bytes of workspace that jpet_mlem_prepare / jpet_mlem_iterate / jpet_loglik_grad need for
+/* Bytes of workspace that jpet_mlem_prepare / jpet_mlem_iterate / jpet_mlem_backproject need for
  * n_events events on this geometry (host output *bytes).  The workspace is any device
- * allocation of at least that size, aligned to 256 bytes.  For jpet_loglik_grad with a
- * sigma_mask, pass a geometry whose sigmas are the mask's (the layout follows the mask). */
+ * allocation of at least that size, aligned to 256 bytes. */
 int jpet_mlem_workspace_size(const jpet_geometry* g, int64_t n_events, size_t* bytes);
 
 /* Iteration-invariant per-event work, done once per event list: direct reconstruction (Eq. 2),
@@ -173,16 +172,22 @@ int jpet_mlem_update(const jpet_geometry* g, const float* s, uint64_t* acc, floa
  *   s:        as for jpet_mlem_iterate (NULL = 1)
  * When a valid event has D_j = 0 the device value l is -inf; if stats is given (the call then
  * synchronises) the call also returns JPET_EDOMAIN in that case.
- * flags = JPET_WS_PREPARED reuses a workspace from jpet_mlem_prepare with this geometry; it is
- * refused (JPET_EINVAL) when sigma_mask differs from the geometry's sigmas, because the prepared
- * kernel constants belong to the sigmas the workspace was prepared with. */
+ * The workspace is sized by jpet_loglik_workspace_size (its layout differs from the MLEM one).
+ * flags = JPET_WS_PREPARED reuses the preparation of an earlier jpet_loglik_grad call on the same
+ * workspace with the same geometry, mask, events and count; it is refused (JPET_EINVAL) when
+ * sigma_mask differs from the geometry's sigmas, because the prepared kernel constants belong to
+ * the sigmas the workspace was prepared with. */
+/* Bytes of workspace jpet_loglik_grad needs for n_events events (host output *bytes); the layout
+ * follows the mask (sigma_mask as for jpet_loglik_grad, nullable). */
+int jpet_loglik_workspace_size(const jpet_geometry* g, const double* sigma_mask, int64_t n_events, size_t* bytes);
+
 int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const float* events, int64_t n,
                      const float* s, const float* rho, double* out3, float* grad_rho, float* D_out, void* ws,
                      size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream);
 
 /* Batched reconstruction: many independent list-mode MLEM problems (each with its own geometry,
- * resolution, event list, sensitivity and image) advanced together, one event-pass launch per
- * iteration for the whole batch.  Each instance's result is that of jpet_mlem_iterate on it alone
+ * resolution, event list, sensitivity and image) advanced together: per iteration, one event-pass
+ * launch for each group of instances that share a kernel configuration (at most a handful).  Each instance's result is that of jpet_mlem_iterate on it alone
  * (to FP32 rounding of the denominators: events are grouped into workgroup batches the same way).
  * Host struct; pointers as for jpet_mlem_iterate. */
 typedef struct jpet_instance {
@@ -231,8 +236,8 @@ typedef struct jpet_launch_info {
 int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_info* info);
 
 /* Kernel timing.  While enabled (enable != 0), every launch of the MLEM event pass made by
- * jpet_mlem_iterate, jpet_mlem_backproject and jpet_mlem_batched_iterate (one per iteration for
- * the whole batch) is bracketed by a pair of HIP events recorded on the caller's stream (the
+ * jpet_mlem_iterate and jpet_mlem_backproject, and every iteration's group of event-pass launches
+ * made by jpet_mlem_batched_iterate, is bracketed by a pair of HIP events recorded on the caller's stream (the
  * stream the kernel runs on).  jpet_profile_read waits for the recorded events, writes the
  * number of timed launches and their summed duration in milliseconds (host outputs, nullable)
  * and forgets them.  Disabling also forgets unread timings.  Process-wide, thread-safe; the

@@ -150,7 +150,7 @@ static void finish_plan(const jpet_geometry* g, int rows_max, int64_t n, Plan& p
   p.tiled = 1;
 }
 
-Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int force_waves) {
+Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int force_waves, bool allow_acc32) {
   Plan none;
   memset(&none, 0, sizeof(none));
   none.ntb = 1;
@@ -176,6 +176,8 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
   //
   // The cheapest candidate under a simple cost model wins, in units of (event, pixel) pairs:
   //   pairs of all events (an ellipse's area at theta = 0) x (1.1 for 16-wave workgroups)
+  //     x (0.82 for 32-bit accumulators: the back-projection's LDS atomics, about 30% of the pass
+  //        with 64-bit ones, run 2.7 times faster on 32-bit words)
   //   + 1.6 x region pixels x workgroup items,
   // the second term being the staging of the image region and the flush of its accumulators
   // (measured at about 1.6 pair evaluations per region pixel); items are the events over the
@@ -185,7 +187,7 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
     size_t budget;
     int acc32;
   };
-  const Cand cands[] = {{8, 72 * 1024, 0}, {16, 150 * 1024, 0}, {16, 150 * 1024, 1}};
+  const Cand cands[] = {{8, 72 * 1024, 0}, {16, 150 * 1024, 0}, {8, 72 * 1024, 1}, {16, 150 * 1024, 1}};
   const double dts[] = {0.0, 0.4, 0.2, 0.1, 0.05, 0.025};
   const int tiles[] = {32, 24, 16, 12, 8};
   const double pairs_per_event = 3.14159265358979323846 * hy_px * (3.0 * msz / sqrt(2.0) / pix);
@@ -194,7 +196,7 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
   double best_cost = 0.0;
   for (const Cand& cd : cands) {
     const int waves = cd.waves;
-    if (rows_max > 64 * waves || (force_waves && waves != force_waves)) continue;
+    if (rows_max > 64 * waves || (force_waves && waves != force_waves) || (cd.acc32 && !allow_acc32)) continue;
     for (double dt : dts) {
       // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
       const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
@@ -230,8 +232,8 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
         }
         finish_plan(g, rows_max, n, p);
         const double items = nn / p.ev_per_wg + (nn < p.nbins ? nn : (double)p.nbins);
-        const double cost =
-            nn * pairs_per_event * (waves == 16 ? 1.1 : 1.0) + 1.6 * items * (double)pitch * (double)W;
+        const double cost = nn * pairs_per_event * (waves == 16 ? 1.1 : 1.0) * (cd.acc32 ? 0.82 : 1.0) +
+                            1.6 * items * (double)pitch * (double)W;
         if (!best.tiled || cost < best_cost) {
           best = p;
           best_cost = cost;
@@ -275,19 +277,19 @@ size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Work
 }
 
 // Layout of a batched workspace: the instance table, then one ordinary workspace per instance.
-// Every binned instance runs with the same wavefront count and register-cache length (those of
-// the most demanding instance) so that one kernel serves the whole batch; the table is sorted by
-// estimated work per workgroup, heaviest first, so that the longest workgroups start earliest.
-struct BatchGroup {  // instances served by one launch (same accumulator width)
+// Each instance keeps its own plan; instances whose plans share a kernel (register-cache length,
+// wavefronts per workgroup, accumulator width) form a group served by one launch per iteration,
+// with the group's largest LDS region.  Within a group the table is sorted by estimated work per
+// workgroup, heaviest first, so that the longest workgroups start earliest.
+struct BatchGroup {
   int first = 0, count = 0;  // table positions
-  int maxlen = 16;
+  int maxlen = 0, waves = 0, acc32 = 0;
   size_t lds = 0;
   int64_t grid = 0;
 };
 
 struct BatchLayout {
-  int waves = 8;
-  BatchGroup group[2];         // 64-bit, then 32-bit LDS accumulators
+  std::vector<BatchGroup> group;
   std::vector<Plan> plan;      // per instance
   std::vector<size_t> off;     // per instance: byte offset of its workspace
   std::vector<int> order;      // table position -> instance
@@ -301,44 +303,44 @@ BatchLayout batch_layout(const jpet_instance* inst, int count) {
   L.plan.resize(count);
   L.off.resize(count);
   L.begin.resize(count);
-  bool need16 = false;
-  for (int k = 0; k < count; ++k) {
-    const Plan p = make_plan(&inst[k].g, inst[k].g.sigma_z, inst[k].g.sigma_dl, inst[k].n);
-    if (p.tiled && p.waves == 16) need16 = true;
-  }
-  L.waves = need16 ? 16 : 8;
   std::vector<double> work(count, 0.0);
+  std::vector<int> key(count, 0);
   for (int k = 0; k < count; ++k) {
     const jpet_geometry& g = inst[k].g;
-    Plan p = make_plan(&g, g.sigma_z, g.sigma_dl, inst[k].n, L.waves);
+    const Plan p = make_plan(&g, g.sigma_z, g.sigma_dl, inst[k].n);
     L.plan[k] = p;
+    // group key: generic instances last
+    key[k] = p.tiled ? (p.maxlen * 100 + p.waves + (p.acc32 ? 10000 : 0)) : 1 << 30;
     if (p.tiled) {
-      BatchGroup& G = L.group[p.acc32 ? 1 : 0];
-      if (p.maxlen > G.maxlen) G.maxlen = p.maxlen;
-      if (p.lds_bytes > G.lds) G.lds = p.lds_bytes;
       // pixels of a typical ellipse (App. B half sizes at theta = 0) times events per workgroup
       work[k] = (1.5 * g.sigma_dl / g.pixel) * (3.0 * g.sigma_z / sqrt(2.0) / g.pixel) * p.ev_per_wg;
     }
     const int64_t np = npix_of(&g);
     if (np > L.max_npix) L.max_npix = np;
   }
-  auto rank = [&](int k) { return L.plan[k].tiled ? (L.plan[k].acc32 ? 1 : 0) : 2; };
   L.order.resize(count);
   for (int k = 0; k < count; ++k) L.order[k] = k;
-  // groups in turn (generic instances last), each by decreasing work; ties keep the caller's order
   std::stable_sort(L.order.begin(), L.order.end(), [&](int a, int b) {
-    if (rank(a) != rank(b)) return rank(a) < rank(b);
+    if (key[a] != key[b]) return key[a] < key[b];
     return work[a] > work[b];
   });
   for (int t = 0; t < count; ++t) {
     const int k = L.order[t];
-    const int r = rank(k);
-    if (r == 2) continue;
-    BatchGroup& G = L.group[r];
-    if (G.count == 0) G.first = t;
+    const Plan& p = L.plan[k];
+    if (!p.tiled) continue;
+    if (L.group.empty() || key[L.order[L.group.back().first]] != key[k]) {
+      BatchGroup G;
+      G.first = t;
+      G.maxlen = p.maxlen;
+      G.waves = p.waves;
+      G.acc32 = p.acc32;
+      L.group.push_back(G);
+    }
+    BatchGroup& G = L.group.back();
     ++G.count;
+    if (p.lds_bytes > G.lds) G.lds = p.lds_bytes;
     L.begin[k] = G.grid;
-    G.grid += L.plan[k].max_items;
+    G.grid += p.max_items;
   }
   size_t off = align_up(sizeof(BatchInst) * (size_t)count, 256);
   for (int k = 0; k < count; ++k) {
@@ -459,6 +461,21 @@ int jpet_mlem_workspace_size(const jpet_geometry* g, int64_t n_events, size_t* b
   return JPET_OK;
 }
 
+int jpet_loglik_workspace_size(const jpet_geometry* g, const double* sigma_mask, int64_t n_events, size_t* bytes) {
+  int rc = check_geometry(g);
+  if (rc) return rc;
+  if (!bytes || n_events < 0) return JPET_EINVAL;
+  double msz = g->sigma_z, mdl = g->sigma_dl;
+  if (sigma_mask) {
+    msz = sigma_mask[0];
+    mdl = sigma_mask[1];
+    if (!finite_pos(msz) || !finite_pos(mdl)) return JPET_EDOMAIN;
+  }
+  const Plan p = make_plan(g, msz, mdl, n_events, 0, false);
+  *bytes = workspace_layout(p, n_events, npix_of(g), nullptr, nullptr);
+  return JPET_OK;
+}
+
 int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_info* info) {
   int rc = check_geometry(g);
   if (rc) return rc;
@@ -574,10 +591,8 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
   }
   // a prepared workspace carries the kernel constants of the sigmas it was prepared with
   if ((flags & JPET_WS_PREPARED) && (msz != g->sigma_z || mdl != g->sigma_dl)) return JPET_EINVAL;
-  Plan p = make_plan(g, msz, mdl, n);
-  // the binned log-likelihood pass accumulates doubles (64-bit region slots); plans with 32-bit
-  // slots use the generic pass, which reads the per-event records every plan keeps
-  if (p.acc32) p.tiled = 0;
+  // the binned log-likelihood pass accumulates doubles: plans with 64-bit region slots only
+  const Plan p = make_plan(g, msz, mdl, n, 0, false);
   Workspace w;
   rc = carve(p, g, n, ws, ws_bytes, &w);
   if (rc) return rc;
@@ -684,9 +699,9 @@ int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t 
     rc = timed(
         [&] {
           hipError_t r = hipSuccess;
-          for (int gi = 0; gi < 2 && r == hipSuccess; ++gi) {
+          for (size_t gi = 0; gi < L.group.size() && r == hipSuccess; ++gi) {
             const BatchGroup& G = L.group[gi];
-            r = launch_event_pass_batched(table + G.first, G.count, G.maxlen, L.waves, gi, G.lds, G.grid, st);
+            r = launch_event_pass_batched(table + G.first, G.count, G.maxlen, G.waves, G.acc32, G.lds, G.grid, st);
           }
           return r;
         },

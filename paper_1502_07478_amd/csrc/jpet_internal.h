@@ -151,8 +151,11 @@ static_assert(sizeof(InstWrite) <= 4096, "InstWrite is passed by value as a kern
 constexpr int RED_SLOTS = 4096;
 constexpr uint32_t kNoBin = 0xffffffffu;
 
-// force_waves: 0 = choose; 8 or 16 = only plans with that many wavefronts per workgroup
-Plan make_plan(const jpet_geometry* g, double mask_sz, double mask_sdl, int64_t n, int force_waves = 0);
+// force_waves: 0 = choose; 8 or 16 = only plans with that many wavefronts per workgroup.
+// allow_acc32: whether regions with 32-bit accumulators may be chosen (not for the
+// log-likelihood pass, which accumulates doubles).
+Plan make_plan(const jpet_geometry* g, double mask_sz, double mask_sdl, int64_t n, int force_waves = 0,
+               bool allow_acc32 = true);
 size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Workspace* out);
 
 // Kernel launchers (return the hipError_t of the launch).

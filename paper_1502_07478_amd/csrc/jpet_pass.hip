@@ -712,6 +712,10 @@ hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxl
     case 3216: return launch_batched<32, 16, false>(table, count, lds_bytes, grid, st);
     case 4816: return launch_batched<48, 16, false>(table, count, lds_bytes, grid, st);
     case 6416: return launch_batched<64, 16, false>(table, count, lds_bytes, grid, st);
+    case 11608: return launch_batched<16, 8, true>(table, count, lds_bytes, grid, st);
+    case 13208: return launch_batched<32, 8, true>(table, count, lds_bytes, grid, st);
+    case 14808: return launch_batched<48, 8, true>(table, count, lds_bytes, grid, st);
+    case 16408: return launch_batched<64, 8, true>(table, count, lds_bytes, grid, st);
     case 11616: return launch_batched<16, 16, true>(table, count, lds_bytes, grid, st);
     case 13216: return launch_batched<32, 16, true>(table, count, lds_bytes, grid, st);
     case 14816: return launch_batched<48, 16, true>(table, count, lds_bytes, grid, st);
@@ -742,6 +746,10 @@ hipError_t launch_event_pass(const Geo& g, const Plan& p, int64_t n, const Works
       case 3216: return launch_tiled<32, 16, false>(g, p, ws, rho, st);
       case 4816: return launch_tiled<48, 16, false>(g, p, ws, rho, st);
       case 6416: return launch_tiled<64, 16, false>(g, p, ws, rho, st);
+      case 11608: return launch_tiled<16, 8, true>(g, p, ws, rho, st);
+      case 13208: return launch_tiled<32, 8, true>(g, p, ws, rho, st);
+      case 14808: return launch_tiled<48, 8, true>(g, p, ws, rho, st);
+      case 16408: return launch_tiled<64, 8, true>(g, p, ws, rho, st);
       case 11616: return launch_tiled<16, 16, true>(g, p, ws, rho, st);
       case 13216: return launch_tiled<32, 16, true>(g, p, ws, rho, st);
       case 14816: return launch_tiled<48, 16, true>(g, p, ws, rho, st);

@@ -90,6 +90,7 @@ def _lib():
         L.jpet_mlem_iterate.argtypes = [gp, vp, i64, vp, vp, i32, vp, sz, u32, sp, vp]
         L.jpet_mlem_backproject.argtypes = [gp, vp, i64, vp, vp, vp, sz, u32, sp, vp]
         L.jpet_mlem_update.argtypes = [gp, vp, vp, vp, vp]
+        L.jpet_loglik_workspace_size.argtypes = [gp, ctypes.POINTER(ctypes.c_double), i64, ctypes.POINTER(sz)]
         L.jpet_loglik_grad.argtypes = [gp, ctypes.POINTER(ctypes.c_double), vp, i64, vp, vp, vp, vp, vp, vp, sz,
                                        u32, sp, vp]
         ip = ctypes.POINTER(Instance)
@@ -361,6 +362,15 @@ class LogLik:
     stats: dict | None
 
 
+def loglik_workspace(g: Geometry, n_events: int, sigma_mask=None, device=None) -> torch.Tensor:
+    """A workspace for jpet_loglik_grad (prepared by its first call, reusable with prepared=True)."""
+    b = ctypes.c_size_t(0)
+    sm = (ctypes.c_double * 2)(*sigma_mask) if sigma_mask is not None else None
+    _check(_lib().jpet_loglik_workspace_size(ctypes.byref(g), sm, int(n_events), ctypes.byref(b)),
+           "jpet_loglik_workspace_size")
+    return torch.empty(int(b.value), dtype=torch.uint8, device=device or "cuda")
+
+
 def loglik_grad(g: Geometry, events: torch.Tensor, rho: torch.Tensor, s: torch.Tensor | None = None,
                 sigma_mask=None, want_grad_rho: bool = True, want_D: bool = False, ws: torch.Tensor | None = None,
                 prepared: bool = False, want_stats: bool = False, stream=None) -> LogLik:
@@ -370,10 +380,7 @@ def loglik_grad(g: Geometry, events: torch.Tensor, rho: torch.Tensor, s: torch.T
         _need(s, "s", torch.float32, g.shape)
     n = events.shape[0]
     if ws is None:
-        # the workspace layout follows the ellipse mask's sigmas
-        gm = g if sigma_mask is None else Geometry(g.R, g.L, float(sigma_mask[0]), float(sigma_mask[1]), g.gamma,
-                                                    g.pixel, g.n_y, g.n_z, g.kernel_variant, 0)
-        ws = workspace(gm, n, rho.device)
+        ws = loglik_workspace(g, n, sigma_mask, rho.device)
         prepared = False
     out3 = torch.zeros(3, dtype=torch.float64, device=rho.device)
     gr = torch.empty(g.shape, dtype=torch.float32, device=rho.device) if want_grad_rho else None

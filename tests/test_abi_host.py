@@ -103,6 +103,12 @@ def test_entry_points_reject_bad_arguments_before_any_device_work(lib):
     bad_mask = (ctypes.c_double * 2)(0.0, 63.0)
     assert lib.jpet_loglik_grad(gp, bad_mask, fake, 5, None, fake, fake, None, None, aligned_ws, 1 << 40, 0, None,
                                 None) == jpet.JPET_EDOMAIN
+    # log-likelihood workspace size: NULL output, negative count, bad mask
+    b = ctypes.c_size_t(0)
+    assert lib.jpet_loglik_workspace_size(gp, None, 5, None) == jpet.JPET_EINVAL
+    assert lib.jpet_loglik_workspace_size(gp, None, -1, ctypes.byref(b)) == jpet.JPET_EINVAL
+    assert lib.jpet_loglik_workspace_size(gp, bad_mask, 5, ctypes.byref(b)) == jpet.JPET_EDOMAIN
+    assert lib.jpet_loglik_workspace_size(gp, None, 5, ctypes.byref(b)) == jpet.JPET_OK and b.value > 0
     # back-projection into a caller accumulator: NULL accumulator, NULL rho, unknown flags, workspace
     assert lib.jpet_mlem_backproject(gp, fake, 5, fake, None, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
     assert lib.jpet_mlem_backproject(gp, fake, 5, None, fake, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL

@@ -101,3 +101,22 @@ def test_grad200_full_size(scale):
     assert sz.grad.item() == pytest.approx(dz, rel=1e-3)
     assert sd.grad.item() == pytest.approx(dd, rel=1e-3)
     assert rel_l2(rho.grad.cpu().numpy(), gr) <= 1e-4
+
+
+def test_loglik_prepared_workspace_reuse():
+    """A workspace prepared by one jpet_loglik_grad call serves later calls on the same events."""
+    w = get_workload("tiny")
+    ev = torch.from_numpy(w.events()).to(DEV)
+    g = jpet.geometry(**w.geometry())
+    s = jpet.sensitivity(g)
+    rho = (s > 0).to(torch.float32)
+    ws = jpet.loglik_workspace(g, ev.shape[0])
+    a = jpet.loglik_grad(g, ev, rho, s=s, ws=ws)
+    b = jpet.loglik_grad(g, ev, rho, s=s, ws=ws, prepared=True)
+    # per-event partial sums meet in LDS and global atomics in no fixed order: equal to rounding
+    va, vb = a.value.cpu().numpy(), b.value.cpu().numpy()
+    np.testing.assert_allclose(va, vb, rtol=1e-9)
+    assert rel_l2(a.grad_rho.cpu().numpy(), b.grad_rho.cpu().numpy()) <= 1e-7
+    # reusing a prepared workspace with another mask is refused
+    with pytest.raises(jpet.JpetError):
+        jpet.loglik_grad(g, ev, rho, s=s, ws=ws, prepared=True, sigma_mask=(w.sigma_z * 1.1, w.sigma_dl))

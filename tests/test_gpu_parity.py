@@ -239,7 +239,7 @@ def test_prod400_sampled_parity(prod):
     rng = np.random.default_rng(0)
     sel = rng.choice(len(ev_np), 2000, replace=False)
     Do, cnt = oracle.denominators_at(go, ev_np, oracle.initial_image(so).ravel(), sel)
-    ll = jpet.loglik_grad(g, ev, rho0, s=s, want_grad_rho=False, want_D=True, ws=ws, prepared=True)
+    ll = jpet.loglik_grad(g, ev, rho0, s=s, want_grad_rho=False, want_D=True)
     Dg = ll.D.double().cpu().numpy()[sel]
     ok = Do > 0
     np.testing.assert_allclose(Dg[ok], Do[ok], rtol=2e-5)
