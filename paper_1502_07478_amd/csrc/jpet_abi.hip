@@ -138,10 +138,16 @@ static void finish_plan(const jpet_geometry* g, int rows_max, int64_t n, Plan& p
   int64_t per = n / 1024;
   if (per < p.ev_per_batch) per = p.ev_per_batch;
   if (per > 128 * p.ev_per_batch) per = 128 * p.ev_per_batch;
-  // 32-bit accumulators hold 2^-24 units: one event adds at most 2^24 to a pixel, so an item's
-  // events must number below 256 to rule out overflow before the flush
-  if (p.acc32 && per > 255) per = 255;
+  // 32-bit accumulators hold 2^-s units: one event adds at most 2^s to a pixel, so an item of up
+  // to 2^(32-s) - 1 events cannot overflow before the flush.  Items of at most 511 events keep
+  // s = 23 (a rounding step of 2^-23 of a count per pair).
+  if (p.acc32 && per > 511) per = 511;
   p.ev_per_wg = (int)((per / p.ev_per_batch) * p.ev_per_batch);
+  if (p.acc32) {
+    int bits = 0;
+    while ((1 << bits) <= p.ev_per_wg) ++bits;  // ev_per_wg < 2^bits
+    p.acc_shift = 32 - bits;
+  }
   const int64_t nonempty = n < p.nbins ? n : p.nbins;
   p.max_items = (n + p.ev_per_wg - 1) / p.ev_per_wg + nonempty;
   if (p.max_items < 1) p.max_items = 1;
@@ -169,74 +175,83 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
     }
   if (maxlen == 0 || rows_max > 64 * 16) return none;  // generic pass
   const int HY = (int)ceil(hy_px + 0.5) + 1;
-  // Candidate regions: 8-wave workgroups whose region fits two per CU; 16-wave workgroups with
-  // one region per CU; the same with 32-bit accumulators (8 bytes per region pixel instead of 12).
-  // For each: no shear or t bins of a given width, square tiles of a given size.  Dynamic LDS
-  // budgets leave room for the static batch buffers within the CU's 160 KB.
+  // Candidate regions: workgroups of 8 or 16 wavefronts, 1 to 4 of them resident per CU (their
+  // LDS regions share the CU's 160 KB with the static batch buffers), 64-bit or 32-bit
+  // accumulators (12 or 8 bytes per region pixel); for each, no shear or t bins of a given width,
+  // and square tiles of a given size.  Residency is also bounded by registers: the event pass
+  // compiled for a register cache of 16/32/48/64 pixels keeps at most 8/6/5/4 wavefronts per SIMD
+  // (its launch bounds guarantee that many).
   //
   // The cheapest candidate under a simple cost model wins, in units of (event, pixel) pairs:
-  //   pairs of all events (an ellipse's area at theta = 0) x (1.1 for 16-wave workgroups)
-  //     x (0.82 for 32-bit accumulators: the back-projection's LDS atomics, about 30% of the pass
-  //        with 64-bit ones, run 2.7 times faster on 32-bit words)
+  //   pairs of all events (an ellipse's area at theta = 0)
+  //     x (4 / wavefronts per SIMD)^0.58  (measured: 6 resident wavefronts per SIMD run the pass
+  //                                        in 0.79 of the time of 4)
+  //     x 1.1 for 16-wave workgroups (more wavefronts meet at every barrier)
+  //     x 0.82 for 32-bit accumulators (the back-projection's LDS atomics, about 30% of the pass
+  //            with 64-bit ones, run 2.7 times faster on 32-bit words)
   //   + 1.6 x region pixels x workgroup items,
   // the second term being the staging of the image region and the flush of its accumulators
-  // (measured at about 1.6 pair evaluations per region pixel); items are the events over the
-  // events per item plus, at most, one partial item per bin.
-  struct Cand {
-    int waves;
-    size_t budget;
-    int acc32;
-  };
-  const Cand cands[] = {{8, 72 * 1024, 0}, {16, 150 * 1024, 0}, {8, 72 * 1024, 1}, {16, 150 * 1024, 1}};
+  // (about 1.6 pair evaluations per region pixel); items are the events over the events per item
+  // plus, at most, one partial item per bin.
+  const int simd_waves = maxlen <= 16 ? 8 : maxlen <= 32 ? 6 : maxlen <= 48 ? 5 : 4;
+  const size_t kLdsPerCU = 160 * 1024, kStatic = 7 * 1024;
   const double dts[] = {0.0, 0.4, 0.2, 0.1, 0.05, 0.025};
   const int tiles[] = {32, 24, 16, 12, 8};
   const double pairs_per_event = 3.14159265358979323846 * hy_px * (3.0 * msz / sqrt(2.0) / pix);
   const double nn = (double)(n > 0 ? n : 1);
   Plan best = none;
   double best_cost = 0.0;
-  for (const Cand& cd : cands) {
-    const int waves = cd.waves;
-    if (rows_max > 64 * waves || (force_waves && waves != force_waves) || (cd.acc32 && !allow_acc32)) continue;
-    for (double dt : dts) {
-      // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
-      const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
-      const double hz = 3.0 * sqrt(0.5 * msz * msz + 0.25 * mdl * mdl * tau * tau);
-      const int HZ = (int)ceil(hz / pix + 1.0) + 1;
-      for (int T : tiles) {
-        // LDS: float image, then the accumulators, column-major with the row pitch rounded up to
-        // the bank alignment; masked reads up to maxlen columns past the image must stay in the
-        // accumulator array (W columns of 4 or 8 bytes)
-        const int RY = T + 2 * HY, W = T + 2 * HZ;
-        const int pitch = (RY + kBankAlign - 1) / kBankAlign * kBankAlign;
-        const size_t bytes = (size_t)pitch * (size_t)W * (cd.acc32 ? 8u : 12u);
-        const int reach = cd.acc32 ? W : 2 * W;
-        // thread words address columns with 8 bits and rows with 9 bits
-        if (bytes > cd.budget || reach < maxlen || W > 256 || RY > 512) continue;
-        Plan p = none;
-        p.maxlen = maxlen;
-        p.HY = HY;
-        p.pitch = pitch;
-        p.waves = waves;
-        p.acc32 = cd.acc32;
-        p.TY = T;
-        p.TZ = T;
-        p.HZ = HZ;
-        p.RY = RY;
-        p.W = W;
-        p.lds_bytes = bytes;
-        if (dt != 0.0) {
-          p.ntb = (int)ceil(2.0 * tmax / dt);
-          if (p.ntb < 1) p.ntb = 1;
-          p.dt = dt;
-          p.tmin = -0.5 * dt * p.ntb;
-        }
-        finish_plan(g, rows_max, n, p);
-        const double items = nn / p.ev_per_wg + (nn < p.nbins ? nn : (double)p.nbins);
-        const double cost = nn * pairs_per_event * (waves == 16 ? 1.1 : 1.0) * (cd.acc32 ? 0.82 : 1.0) +
-                            1.6 * items * (double)pitch * (double)W;
-        if (!best.tiled || cost < best_cost) {
-          best = p;
-          best_cost = cost;
+  for (int waves : {8, 16}) {
+    if (rows_max > 64 * waves || (force_waves && waves != force_waves)) continue;
+    for (int wgs = 1; wgs <= 4; ++wgs) {
+      const int occ = wgs * waves / 4;  // resident wavefronts per SIMD
+      if (occ > simd_waves) continue;
+      const size_t budget = kLdsPerCU / (size_t)wgs - kStatic;
+      const double occ_factor = pow(4.0 / (double)occ, 0.58) * (waves == 16 ? 1.1 : 1.0);
+      for (int acc32 = 0; acc32 <= 1; ++acc32) {
+        if (acc32 && !allow_acc32) continue;
+        for (double dt : dts) {
+          // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
+          const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
+          const double hz = 3.0 * sqrt(0.5 * msz * msz + 0.25 * mdl * mdl * tau * tau);
+          const int HZ = (int)ceil(hz / pix + 1.0) + 1;
+          for (int T : tiles) {
+            // LDS: float image, then the accumulators, column-major with the row pitch rounded
+            // up to the bank alignment; masked reads up to maxlen columns past the image must stay
+            // in the accumulator array (W columns of 4 or 8 bytes)
+            const int RY = T + 2 * HY, W = T + 2 * HZ;
+            const int pitch = (RY + kBankAlign - 1) / kBankAlign * kBankAlign;
+            const size_t bytes = (size_t)pitch * (size_t)W * (acc32 ? 8u : 12u);
+            const int reach = acc32 ? W : 2 * W;
+            // thread words address columns with 8 bits and rows with 9 bits
+            if (bytes > budget || reach < maxlen || W > 256 || RY > 512) continue;
+            Plan p = none;
+            p.maxlen = maxlen;
+            p.HY = HY;
+            p.pitch = pitch;
+            p.waves = waves;
+            p.acc32 = acc32;
+            p.TY = T;
+            p.TZ = T;
+            p.HZ = HZ;
+            p.RY = RY;
+            p.W = W;
+            p.lds_bytes = bytes;
+            if (dt != 0.0) {
+              p.ntb = (int)ceil(2.0 * tmax / dt);
+              if (p.ntb < 1) p.ntb = 1;
+              p.dt = dt;
+              p.tmin = -0.5 * dt * p.ntb;
+            }
+            finish_plan(g, rows_max, n, p);
+            const double items = nn / p.ev_per_wg + (nn < p.nbins ? nn : (double)p.nbins);
+            const double cost = nn * pairs_per_event * occ_factor * (acc32 ? 0.82 : 1.0) +
+                                1.6 * items * (double)pitch * (double)W;
+            if (!best.tiled || cost < best_cost) {
+              best = p;
+              best_cost = cost;
+            }
+          }
         }
       }
     }

@@ -78,7 +78,8 @@ struct Plan {
   double tmin, dt;      // t bin b spans [tmin + b dt, tmin + (b+1) dt); ntb == 1: no shear
   int maxlen;           // register cache length (16/32/48/64) >= longest ellipse row
   int waves;            // wavefronts per workgroup
-  int acc32;            // 1: 32-bit LDS accumulators in 2^-24 units (regions too large for 64-bit ones)
+  int acc32;            // 1: 32-bit LDS accumulators in 2^-acc_shift units
+  int acc_shift;        // 32 - bits of the largest item size (events): no 32-bit slot overflows
   int ev_per_batch;     // events whose rows are processed together (rows <= 64 * waves)
   int ev_per_wg;        // events per workgroup item (a multiple of ev_per_batch)
   int64_t max_items;    // upper bound of workgroup items (the launch grid)

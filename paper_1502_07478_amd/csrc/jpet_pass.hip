@@ -231,7 +231,10 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   static_assert(!(GRAD && ACC32), "the log-likelihood pass accumulates doubles");
   using AccT = typename std::conditional<ACC32, unsigned, unsigned long long>::type;
   AccT* acc_s = reinterpret_cast<AccT*>(smem + (size_t)npx * sizeof(float));
-  constexpr float kUnit = ACC32 ? 16777216.0f : 4294967296.0f;  // accumulator units per count
+  // accumulator units per count: 2^32, or 2^acc_shift for 32-bit slots (the plan keeps an item's
+  // events below 2^(32 - acc_shift), so no slot can overflow before the flush)
+  const float kUnit = ACC32 ? __builtin_ldexpf(1.0f, p.acc_shift) : 4294967296.0f;
+  const int flush_shift = ACC32 ? 32 - p.acc_shift : 0;
 
   const int tz = it.bin % p.ntz;
   const int rest = it.bin / p.ntz;
@@ -462,7 +465,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   for (int cl = wave; cl < p.W; cl += WAVES) {
     const int kc = kbase + cl;
     for (int rl = lane; rl < p.RY; rl += WAVE) {
-      const unsigned long long a = (unsigned long long)acc_s[cl * pitch + rl] << (ACC32 ? 8 : 0);
+      const unsigned long long a = (unsigned long long)acc_s[cl * pitch + rl] << flush_shift;
       if (a == 0ull) continue;
       const int r = rbase + rl;
       const int k = kc + ps.off[rl];
@@ -491,8 +494,15 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   }
 }
 
+// Resident wavefronts per SIMD the tiled pass is compiled for (the plan's cost model assumes
+// them): the register cache of MAXLEN pixels leaves room for 8, 6, 5 or 4.
+template <int MAXLEN>
+constexpr int pass_waves_per_simd() {
+  return MAXLEN <= 16 ? 8 : MAXLEN <= 32 ? 6 : MAXLEN <= 48 ? 5 : 4;
+}
+
 template <int MAXLEN, int WAVES, bool ACC32, int PITCH>
-__global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_tiled(Geo g, Plan p,
+__global__ void __launch_bounds__(WAVES * 64, pass_waves_per_simd<MAXLEN>()) k_event_pass_tiled(Geo g, Plan p,
                                                                     const unsigned char* __restrict__ blocks,
                                                                     const BinItem* __restrict__ items,
                                                                     const float* __restrict__ rho,
