@@ -156,7 +156,8 @@ static void finish_plan(const jpet_geometry* g, int rows_max, int64_t n, Plan& p
   p.tiled = 1;
 }
 
-Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int force_waves, bool allow_acc32) {
+Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int force_waves, bool loglik) {
+  const bool allow_acc32 = !loglik;
   Plan none;
   memset(&none, 0, sizeof(none));
   none.ntb = 1;
@@ -193,7 +194,8 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
   // the second term being the staging of the image region and the flush of its accumulators
   // (about 1.6 pair evaluations per region pixel); items are the events over the events per item
   // plus, at most, one partial item per bin.
-  const int simd_waves = maxlen <= 16 ? 8 : maxlen <= 32 ? 6 : maxlen <= 48 ? 5 : 4;
+  // (the log-likelihood pass, with its derivative terms, keeps 5 / 4 / 4 / 4)
+  const int simd_waves = loglik ? (maxlen <= 16 ? 5 : 4) : maxlen <= 16 ? 8 : maxlen <= 32 ? 6 : maxlen <= 48 ? 5 : 4;
   const size_t kLdsPerCU = 160 * 1024, kStatic = 7 * 1024;
   const double dts[] = {0.0, 0.4, 0.2, 0.1, 0.05, 0.025};
   const int tiles[] = {32, 24, 16, 12, 8};
@@ -486,7 +488,7 @@ int jpet_loglik_workspace_size(const jpet_geometry* g, const double* sigma_mask,
     mdl = sigma_mask[1];
     if (!finite_pos(msz) || !finite_pos(mdl)) return JPET_EDOMAIN;
   }
-  const Plan p = make_plan(g, msz, mdl, n_events, 0, false);
+  const Plan p = make_plan(g, msz, mdl, n_events, 0, true);
   *bytes = workspace_layout(p, n_events, npix_of(g), nullptr, nullptr);
   return JPET_OK;
 }
@@ -607,7 +609,7 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
   // a prepared workspace carries the kernel constants of the sigmas it was prepared with
   if ((flags & JPET_WS_PREPARED) && (msz != g->sigma_z || mdl != g->sigma_dl)) return JPET_EINVAL;
   // the binned log-likelihood pass accumulates doubles: plans with 64-bit region slots only
-  const Plan p = make_plan(g, msz, mdl, n, 0, false);
+  const Plan p = make_plan(g, msz, mdl, n, 0, true);
   Workspace w;
   rc = carve(p, g, n, ws, ws_bytes, &w);
   if (rc) return rc;

@@ -153,10 +153,10 @@ constexpr int RED_SLOTS = 4096;
 constexpr uint32_t kNoBin = 0xffffffffu;
 
 // force_waves: 0 = choose; 8 or 16 = only plans with that many wavefronts per workgroup.
-// allow_acc32: whether regions with 32-bit accumulators may be chosen (not for the
-// log-likelihood pass, which accumulates doubles).
+// loglik: plan for the log-likelihood pass (64-bit region slots for its doubles, its own register
+// budget) instead of the MLEM pass.
 Plan make_plan(const jpet_geometry* g, double mask_sz, double mask_sdl, int64_t n, int force_waves = 0,
-               bool allow_acc32 = true);
+               bool loglik = false);
 size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Workspace* out);
 
 // Kernel launchers (return the hipError_t of the launch).

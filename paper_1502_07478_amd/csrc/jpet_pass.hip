@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(WAVES * 64, pass_waves_per_simd<MAXLEN>()) k_e
 // The log-likelihood pass on the binned layout (B: double image of sum P / D, zeroed by the
 // caller; red[0..2]: log D', Du / D', Dw / D' sums, zeroed by the caller).
 template <int MAXLEN, int WAVES>
-__global__ void __launch_bounds__(WAVES * 64, 4) k_loglik_tiled(Geo g, Plan p, const unsigned char* __restrict__ blocks,
+__global__ void __launch_bounds__(WAVES * 64, MAXLEN <= 16 ? 5 : 4) k_loglik_tiled(Geo g, Plan p, const unsigned char* __restrict__ blocks,
                                                                 const BinItem* __restrict__ items,
                                                                 const float* __restrict__ rho, double* __restrict__ B,
                                                                 float* __restrict__ D_out, double* __restrict__ red,
