@@ -7,7 +7,7 @@
  *   - events are the triples (z_u, z_d, dl) of the Setup section (Eq. 1),
  *   - the per-pixel sensitivity is Eq. 4,
  *   - the event kernel P(e|i) is Eq. 7 with the vectors of Eq. 8-11 and the diagonal
- *     C^-1 of Eq. 12 (gamma = 0),
+ *     C^-1 of Eq. 12 (including its off-diagonal gamma),
  *   - it is evaluated over the pixel centres inside the 3-sigma ellipse of each event
  *     (Sec. 3, last paragraph; bounding box of App. B),
  *   - one iteration is the two-pass scheme of the implementation listing (Sec. 4):
@@ -55,19 +55,21 @@ enum jpet_status {
   JPET_EDOMAIN = -2,    /* geometry out of domain (see jpet_geometry); log-likelihood is -inf */
   JPET_EWORKSPACE = -3, /* workspace NULL or smaller than the size query returned */
   JPET_EHIP = -4,       /* a HIP runtime call failed; jpet_last_hip_error() has its code */
-  JPET_ENOTSUP = -5     /* valid request that this build does not implement (e.g. gamma != 0) */
+  JPET_ENOTSUP = -5     /* valid request that this build does not implement */
 };
 
 /* Detector, resolution and pixel grid.  All members are read by value; the struct is
  * host memory.  Domain (else JPET_EDOMAIN): R, L, sigma_z, sigma_dl, pixel finite and > 0;
  * 0 < n_y, n_z <= 32768; n_y * pixel / 2 < R (every pixel centre lies between the strips);
- * kernel_variant in {0, 1}.  gamma must be 0 (else JPET_ENOTSUP). */
+ * kernel_variant in {0, 1}; gamma finite with 2 gamma^2 < sigma_z^-2 sigma_dl^-2 (C^-1 of Eq. 12
+ * positive definite). */
 typedef struct jpet_geometry {
   double R;              /* strip half-separation: strips at y = +R and y = -R (Setup, Eq. 1) */
   double L;              /* strip length; strips span z in [-L/2, L/2] (Eq. 4) */
   double sigma_z;        /* resolution of z_u and z_d (Eq. 12) */
   double sigma_dl;       /* resolution of dl (Eq. 12) */
-  double gamma;          /* off-diagonal element of C^-1 (Eq. 12); must be 0 */
+  double gamma;          /* off-diagonal element of C^-1 (Eq. 12): C^-1 = [[u, 0, g], [0, u, -g],
+                            [g, -g, w]], u = sigma_z^-2, w = sigma_dl^-2, in mm^-2 */
   double pixel;          /* pixel pitch, the same along y and z */
   int32_t n_y;           /* number of pixel rows (y) */
   int32_t n_z;           /* number of pixel columns (z) */

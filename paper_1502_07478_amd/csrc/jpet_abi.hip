@@ -49,7 +49,11 @@ int check_geometry(const jpet_geometry* g) {
   if (!(0.5 * (double)g->n_y * g->pixel < g->R)) return JPET_EDOMAIN;
   if (g->kernel_variant != 0 && g->kernel_variant != 1) return JPET_EDOMAIN;
   if (!isfinite(g->gamma)) return JPET_EDOMAIN;
-  if (g->gamma != 0.0) return JPET_ENOTSUP;
+  // C^-1 (Eq. 12) must be positive definite: u > 0, w > 0 and u^2 w - 2 u gamma^2 > 0
+  {
+    const double u = 1.0 / (g->sigma_z * g->sigma_z), w = 1.0 / (g->sigma_dl * g->sigma_dl);
+    if (!(2.0 * g->gamma * g->gamma < u * w)) return JPET_EDOMAIN;
+  }
   if (g->reserved != 0) return JPET_EINVAL;
   return JPET_OK;
 }
@@ -67,6 +71,13 @@ Geo make_geo(const jpet_geometry* g, double mask_sz, double mask_sdl) {
   o.um = 1.0 / (mask_sz * mask_sz);
   o.wm = 1.0 / (mask_sdl * mask_sdl);
   o.fa = g->kernel_variant ? 2.0 : 1.0;
+  o.gamma = g->gamma;
+  {
+    const double det = o.u * o.u * o.w - 2.0 * o.u * o.gamma * o.gamma;
+    o.cnorm = sqrt(det) / (2.0 * 3.14159265358979323846);
+    o.cu = (2.0 * o.u * o.w - 2.0 * o.gamma * o.gamma) / (2.0 * det);
+    o.cw = o.u * o.u / (2.0 * det);
+  }
   o.y0 = (0.5 - 0.5 * (double)g->n_y) * g->pixel;
   o.z0 = (0.5 - 0.5 * (double)g->n_z) * g->pixel;
   o.n_y = g->n_y;
@@ -426,7 +437,7 @@ const char* jpet_strerror(int status) {
     case JPET_EDOMAIN: return "argument out of domain (geometry, resolution or grid) or log-likelihood is -inf";
     case JPET_EWORKSPACE: return "workspace missing, misaligned or smaller than jpet_mlem_workspace_size";
     case JPET_EHIP: return "HIP runtime error (see jpet_last_hip_error)";
-    case JPET_ENOTSUP: return "not supported by this build (gamma != 0)";
+    case JPET_ENOTSUP: return "not supported by this build";
     default: return "unknown status";
   }
 }

@@ -92,13 +92,13 @@ __device__ inline bool row_interval(const Geo& g, const EventRec& e, int i, int*
   return true;
 }
 
-// Single-precision constants of the kernel along one pixel row (Eq. 7-11 with gamma = 0).
+// Single-precision constants of the kernel along one pixel row (Eq. 7-12).
 // With Y the row's y, dy = Y - y~ and b1 = z - z~ - dy tan the running coordinate:
 //   kappa = aC^-1a + 2 oC^-1b = 2u c^4 (R^2 + Y^2) + w fa^2 Y^2 c^2 t^2 + 4 w c^2 (1 + 2t^2) Y dy
 //                              - 4 u t c^2 Y b1
 //   gamma = bC^-1a           = 2 fa w c^2 t Y dy - 2 u c^2 Y b1
 //   q     = bC^-1b           = 2 u b1^2 + 4 w c^2 dy^2
-// and P / (u sqrt(w) / 2 pi) = kappa^-1/2 exp2(S (gamma^2 / kappa - q)) with S = log2(e) / 2.
+// and P / cnorm = kappa^-1/2 exp2(S (gamma^2 / kappa - q)) with S = log2(e) / 2.
 struct RowK {
   float b10, pix;    // b1 at the row's first pixel and its step
   float kap0, dkap;  // kappa at the first pixel and its step
@@ -115,9 +115,12 @@ __device__ inline RowK row_constants(const Geo& g, const EventRec& e, int i, int
   const double zc = e.z + t * dy;
   const double b10 = g.z0 + (double)klo * g.pixel - zc;
   const double kap_r = 2.0 * u * c2 * c2 * (g.R * g.R + Y * Y) + w * f * f * Y * Y * c2 * t * t +
-                       4.0 * w * c2 * (1.0 + 2.0 * t * t) * Y * dy;
+                       4.0 * w * c2 * (1.0 + 2.0 * t * t) * Y * dy +
+                       -4.0 * g.gamma * g.R * c2 * c * t * (f * Y + 2.0 * dy);
   const double kap_b = -4.0 * u * t * c2 * Y;
-  const double gam_r = 2.0 * f * w * c2 * t * Y * dy;
+  // gamma (Eq. 12): kappa += -4 gamma R c^3 t (f Y + 2 dy), gamma^ += -4 gamma R c^3 dy
+  const double c3g = -4.0 * g.gamma * g.R * c2 * c;
+  const double gam_r = 2.0 * f * w * c2 * t * Y * dy + c3g * dy;
   const double gam_b = -2.0 * u * c2 * Y;
   const double rs = 0.84932180028801904272;  // sqrt(log2(e) / 2)
   RowK r;
@@ -134,7 +137,7 @@ __device__ inline RowK row_constants(const Geo& g, const EventRec& e, int i, int
   return r;
 }
 
-// P / (u sqrt(w) / 2 pi) at the j-th pixel of the row; kappa must be positive.
+// P / cnorm at the j-th pixel of the row; kappa must be positive.
 __device__ inline float kernel_fast(const RowK& r, float jf) {
   const float b1 = fmaf(jf, r.pix, r.b10);
   const float kap = fmaf(jf, r.dkap, r.kap0);

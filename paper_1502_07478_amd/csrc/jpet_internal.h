@@ -15,6 +15,10 @@ struct Geo {
   double um, wm;       // the same for the 3-sigma ellipse mask (equal to u, w except for gradients)
   double fa;           // factor of the third component of a (Eq. 9): 1 as printed, 2 exact
   double y0, z0;       // centre of pixel (0, 0)
+  double gamma;        // off-diagonal element of C^-1 (Eq. 12)
+  double cnorm;        // sqrt(det C^-1) / (2 pi), det C^-1 = u^2 w - 2 u gamma^2: P = cnorm P'
+  double cu, cw;       // (d det / du) / (2 det) and (d det / dw) / (2 det): the prefactor's share
+                       // of d log P / du and d log P / dw
   int32_t n_y, n_z;
 };
 
@@ -33,7 +37,7 @@ struct EventRec {
 };
 
 // Per-event constants of the binned event pass (64 bytes), written at prepare time.  With Y the
-// row's y, dy = Y - y~ and b1 = z - z~ - dy tan (Eq. 8-11, gamma = 0):
+// row's y, dy = Y - y~ and b1 = z - z~ - dy tan (Eq. 8-12):
 //   kappa = aC^-1a + 2 oC^-1b = A1 (R^2 + Y^2) + A2 Y^2 + A3 Y dy + KB Y b1
 //   gamma = bC^-1a           = G1 Y dy + GB Y b1
 //   S q   = S bC^-1b         = S 2u b1^2 + Q3s dy^2            (S = log2(e) / 2)
@@ -44,7 +48,8 @@ struct EvConst {
   float t;              // tan(theta~)
   float A1, A2, A3, KB; // 2u c^4, w fa^2 c^2 t^2, 4 w c^2 (1 + 2t^2), -4 u t c^2
   float G1, GB, Q3s;    // 2 fa w c^2 t, -2 u c^2, S 4 w c^2
-  int32_t pad[4];
+  float GK, GG;          // gamma terms: kappa += GK (fa y + 2 dy), gamma^ += GG dy (-4 g R c^3 t, -4 g R c^3)
+  int32_t pad[2];
 };
 
 static_assert(sizeof(EvConst) == 64, "EvConst is copied to LDS in 16-byte units");

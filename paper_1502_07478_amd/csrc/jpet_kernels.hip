@@ -39,16 +39,18 @@ __global__ void k_fill_f64(double* p, int64_t n) {
 // ------------------------------------------------------------------------------------------
 // log-likelihood and gradient
 
-// d log P / du and d log P / dw at a pixel (gamma = 0), from the quadratic forms' parts:
-//   kappa = u Kz + w Kl, gamma = u Gz + w Gl, q = u Bz + w Bl,
-//   dlogP/du = 1/u - Kz/(2 kappa) - (Bz - 2 (gamma/kappa) Gz + (gamma/kappa)^2 Kz) / 2
-//   dlogP/dw = 1/(2w) - Kl/(2 kappa) - (Bl - 2 (gamma/kappa) Gl + (gamma/kappa)^2 Kl) / 2
+// d log P / du and d log P / dw at a pixel, from the quadratic forms' parts:
+//   kappa = u Kz + w Kl + gamma Kg, gamma^ = u Gz + w Gl + gamma Gg, q = u Bz + w Bl,
+//   dlogP/du = cu - Kz/(2 kappa) - (Bz - 2 (gamma^/kappa) Gz + (gamma^/kappa)^2 Kz) / 2
+//   dlogP/dw = cw - Kl/(2 kappa) - (Bl - 2 (gamma^/kappa) Gl + (gamma^/kappa)^2 Kl) / 2
+// with cu, cw the prefactor's share (1/u and 1/(2w) for gamma = 0).
 struct RowG {
   float b10, pix;
   float kz0, kzb;   // Kz = kz0 + kzb b1
   float gzb;        // Gz = gzb b1
   float kl, gl, bl; // row constants
-  float u, w;
+  float kg, gg;     // gamma Kg and gamma Gg (row constants)
+  float u, w, cu, cw;
 };
 
 __device__ inline RowG row_gradient_constants(const Geo& g, const EventRec& e, int i, int klo) {
@@ -65,8 +67,12 @@ __device__ inline RowG row_gradient_constants(const Geo& g, const EventRec& e, i
   r.kl = (float)(f * f * Y * Y * c2 * t * t + 4.0 * c2 * (1.0 + 2.0 * t * t) * Y * dy);
   r.gl = (float)(2.0 * f * c2 * t * Y * dy);
   r.bl = (float)(4.0 * c2 * dy * dy);
+  r.kg = (float)(-4.0 * g.gamma * g.R * c2 * c * t * (f * Y + 2.0 * dy));
+  r.gg = (float)(-4.0 * g.gamma * g.R * c2 * c * dy);
   r.u = (float)g.u;
   r.w = (float)g.w;
+  r.cu = (float)g.cu;
+  r.cw = (float)g.cw;
   return r;
 }
 
@@ -75,17 +81,17 @@ __device__ inline void dlogp(const RowG& r, float jf, float* du, float* dw) {
   const float kz = fmaf(r.kzb, b1, r.kz0);
   const float gz = r.gzb * b1;
   const float bz = 2.0f * b1 * b1;
-  const float kap = r.u * kz + r.w * r.kl;
-  const float gam = r.u * gz + r.w * r.gl;
+  const float kap = r.u * kz + r.w * r.kl + r.kg;
+  const float gam = r.u * gz + r.w * r.gl + r.gg;
   const float ik = 1.0f / kap;
   const float gk = gam * ik;
-  *du = 1.0f / r.u - 0.5f * kz * ik - 0.5f * (bz - 2.0f * gk * gz + gk * gk * kz);
-  *dw = 0.5f / r.w - 0.5f * r.kl * ik - 0.5f * (r.bl - 2.0f * gk * r.gl + gk * gk * r.kl);
+  *du = r.cu - 0.5f * kz * ik - 0.5f * (bz - 2.0f * gk * gz + gk * gk * kz);
+  *dw = r.cw - 0.5f * r.kl * ik - 0.5f * (r.bl - 2.0f * gk * r.gl + gk * gk * r.kl);
 }
 
 // Grid-stride over events, one wavefront per event, one lane per ellipse row.  Per block: double
 // partial sums of log D', (sum_i rho_i P'_i dlogP_i/du) / D' and the same for w, where
-// D' = sum_i rho_i P'_i and P' = P / (u sqrt(w) / 2 pi); written to red[3 * block + c].
+// D' = sum_i rho_i P'_i and P' = P / cnorm; written to red[3 * block + c].
 // With B given, sum_j P'_jl / D'_j (= sum_j P_jl / D_j) is added into B with double atomics.
 __global__ void __launch_bounds__(256) k_loglik_pass(Geo g, int64_t n, const EventRec* __restrict__ ev,
                                                      const float* __restrict__ rho, double* __restrict__ B,
@@ -94,7 +100,7 @@ __global__ void __launch_bounds__(256) k_loglik_pass(Geo g, int64_t n, const Eve
   const int lane = threadIdx.x & (WAVE - 1);
   const int wave = threadIdx.x / WAVE;
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
-  const float norm = (float)(g.u * sqrt(g.w) / (2.0 * kPi));
+  const float norm = (float)g.cnorm;
   double s_log = 0.0, s_du = 0.0, s_dw = 0.0;
   unsigned long long nzero = 0, nbad_tot = 0;
   for (int64_t j = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wave; j < n; j += nwaves) {
@@ -197,8 +203,8 @@ __global__ void __launch_bounds__(256) k_loglik_finish(Geo g, int nblocks, const
   if (threadIdx.x == 0) {
     const double nvalid = (double)cnt[C_VALID];
     const double nz = (double)cnt[C_ZERO_DEN];
-    // log(D / pi) = log D' + log(u sqrt(w) / (2 pi) / pi)
-    const double lognorm = log(g.u * sqrt(g.w) / (2.0 * kPi) / kPi);
+    // log(D / pi) = log D' + log(cnorm / pi)
+    const double lognorm = log(g.cnorm / kPi);
     const double ll = sh[0][0] + (nvalid - nz) * lognorm - sh[3][0];
     out3[0] = nz > 0.0 ? -INFINITY : ll;
     out3[1] = sh[1][0] * (-2.0 * g.u / g.sigma_z);

@@ -11,7 +11,7 @@
 // image with one atomic per touched pixel.  Integer accumulation makes the new image exact
 // and independent of the order in which events are processed.
 //
-// The constant factor u sqrt(w) / (2 pi) of Eq. 7 cancels in m / D and is not applied.
+// The constant factor sqrt(det C^-1) / (2 pi) of Eq. 7 cancels in m / D and is not applied.
 #include <type_traits>
 
 #include "jpet_device.h"
@@ -31,10 +31,13 @@ struct PassShared {
   unsigned zero, bad;
 };
 
-// Single-precision kernel constants along one pixel row (Eq. 7-11, gamma = 0); j is the pixel's
+// Single-precision kernel constants along one pixel row (Eq. 7-12); j is the pixel's
 // offset in the row:
 //   kappa_j = kap0 + j dkap,  sqrt(S) gamma_j = gs0 + j dgs,  S q_j = (qa j + qb) j + qc
-// and P / (u sqrt(w) / 2 pi) = kappa^-1/2 exp2(S gamma^2 / kappa - S q), S = log2(e) / 2.
+// and P / (sqrt(det C^-1) / 2 pi) = kappa^-1/2 exp2(S gamma^2 / kappa - S q), S = log2(e) / 2.
+// The off-diagonal gamma of C^-1 enters only kappa and gamma^ through per-row constants: with
+// b1 = b2, the gamma terms of b C^-1 b cancel (so the ellipse does not depend on gamma) while
+// kappa gains -4 gamma R c^3 t (fa y + 2 dy) and gamma^ gains -4 gamma R c^3 dy.
 struct RowF {
   float kap0, dkap, gs0, dgs, qb, qc;
 };
@@ -113,11 +116,12 @@ __device__ __forceinline__ void pass2(const float (&m)[MAXLEN], float sc, int ba
 }
 
 // Log-likelihood mode.  Per pixel, besides P' (the kernel without its constant factor), the
-// derivatives of log P with respect to u = sigma_z^-2 and w = sigma_dl^-2 (gamma = 0), written with
-// kappa = u Kz + w Kl, gamma = u Gz + w Gl, q = u Bz + w Bl, Bz = 2 b1^2, g = gamma / kappa and
-// h = 1/kappa + g^2:
-//   dlogP/du = 1/u - b1^2 + g Gz - Kz h / 2,    dlogP/dw = 1/(2w) - Bl/2 + g Gl - Kl h / 2.
-// Along a row Kz and Gz are affine in the pixel offset j; Kl, Gl, Bl are constant.
+// derivatives of log P with respect to u = sigma_z^-2 and w = sigma_dl^-2, written with
+// kappa = u Kz + w Kl + gamma Kg, gamma^ = u Gz + w Gl + gamma Gg, q = u Bz + w Bl, Bz = 2 b1^2,
+// g = gamma^ / kappa and h = 1/kappa + g^2:
+//   dlogP/du = cu - b1^2 + g Gz - Kz h / 2,    dlogP/dw = cw - Bl/2 + g Gl - Kl h / 2,
+// cu, cw being the prefactor's share (1/u and 1/(2w) for gamma = 0).  Along a row Kz and Gz are
+// affine in the pixel offset j; Kl, Gl, Bl are constant.
 struct RowD {
   float b10, Kzh0, dKzh, Gz0, dGz, Gl, Klh, cw;  // Kzh = Kz / 2, Klh = Kl / 2, cw = 1/(2w) - Bl/2
 };
@@ -251,6 +255,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   const float qa = S2u * pixf * pixf;
   const float R2 = (float)(g.R * g.R);
   const float rs = 0.84932180028801904272f;  // sqrt(log2(e) / 2)
+  const float faf = (float)g.fa;
   const int nbatch = (it.count + p.ev_per_batch - 1) / p.ev_per_batch;
   const int cbytes = p.ev_per_batch * (int)sizeof(EvConst);
   const unsigned char* blk0 = blocks + (size_t)it.batch * (size_t)p.batch_bytes;
@@ -278,9 +283,10 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   double s_log = 0.0, s_du = 0.0, s_dw = 0.0;
   int pidx = -1;  // input index of event tid of the previous batch
   const float iu = (float)(1.0 / g.u), iw = (float)(1.0 / g.w);
+  const float cuf = (float)g.cu, cwf = (float)g.cw;  // prefactor terms of d log P / du, dw
   const float irs = 1.1774100225154747f;     // 1 / sqrt(log2(e) / 2)
   const float iS = 1.3862943611198906f;      // 1 / (log2(e) / 2)
-  const float Dnorm = (float)(g.u * sqrt(g.w) / (2.0 * kPi));
+  const float Dnorm = (float)g.cnorm;
   if (tid == 0) {
     ps.zero = 0u;
     ps.bad = 0u;
@@ -377,12 +383,12 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
         const float Y = fmaf(rlf, pixf, Yb);
         const float dy = fmaf(rlf, pixf, -c.yr);
         const float b10 = fmaf((float)(kl + ps.off[rl]), pixf, -fmaf(c.t, dy, c.zr));
-        const float kr = fmaf(c.A1, R2 + Y * Y, Y * fmaf(c.A2, Y, c.A3 * dy));
+        const float kr = fmaf(c.GK, fmaf(faf, Y, 2.0f * dy), fmaf(c.A1, R2 + Y * Y, Y * fmaf(c.A2, Y, c.A3 * dy)));
         const float kb = c.KB * Y;
         const float gb = c.GB * Y;
         rk.kap0 = fmaf(kb, b10, kr);
         rk.dkap = kb * pixf;
-        rk.gs0 = rs * fmaf(gb, b10, c.G1 * Y * dy);
+        rk.gs0 = rs * fmaf(gb, b10, fmaf(c.GG, dy, c.G1 * Y * dy));
         rk.dgs = rs * gb * pixf;
         rk.qb = 2.0f * S2u * b10 * pixf;
         rk.qc = fmaf(S2u * b10, b10, c.Q3s * dy * dy);
@@ -394,7 +400,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
           rd.dGz = iu * gb * pixf;
           rd.Gl = iw * c.G1 * Y * dy;
           rd.Klh = 0.5f * iw * Y * fmaf(c.A2, Y, c.A3 * dy);
-          rd.cw = 0.5f * iw * (1.0f - iS * c.Q3s * dy * dy);
+          rd.cw = cwf - 0.5f * iS * iw * c.Q3s * dy * dy;
         }
         const float kend = fmaf((float)(len - 1), rk.dkap, rk.kap0);
         safe = rk.kap0 > 1e-3f * fabsf(rk.kap0) && kend > 1e-3f * fabsf(rk.kap0);
@@ -406,9 +412,9 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       float D, Du = 0.0f, Dw = 0.0f;
       if constexpr (GRAD) {
         if (__any(!safe)) {
-          pass1g<MAXLEN, true>(rk, rd, qa, pixf, iu, irs, rho_s, base, pitch, len, wn, wl, m, &bad, D, Du, Dw);
+          pass1g<MAXLEN, true>(rk, rd, qa, pixf, cuf, irs, rho_s, base, pitch, len, wn, wl, m, &bad, D, Du, Dw);
         } else {
-          pass1g<MAXLEN, false>(rk, rd, qa, pixf, iu, irs, rho_s, base, pitch, len, wn, wl, m, &bad, D, Du, Dw);
+          pass1g<MAXLEN, false>(rk, rd, qa, pixf, cuf, irs, rho_s, base, pitch, len, wn, wl, m, &bad, D, Du, Dw);
         }
       } else {
         if (__any(!safe)) {

@@ -250,7 +250,12 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
       k.G1 = 2.0f * fa * w * c2 * t;
       k.GB = -2.0f * u * c2;
       k.Q3s = (float)kHalfLog2e * 4.0f * w * c2;
-      k.pad[0] = k.pad[1] = k.pad[2] = k.pad[3] = 0;
+      {
+        const double c3 = e.c * e.c * e.c;
+        k.GK = (float)(-4.0 * g.gamma * g.R * c3 * e.t);
+        k.GG = (float)(-4.0 * g.gamma * g.R * c3);
+      }
+      k.pad[0] = k.pad[1] = 0;
       evc[tid] = k;
     }
     __syncthreads();

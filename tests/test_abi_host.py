@@ -62,7 +62,10 @@ GOOD = dict(R=450.0, L=500.0, sigma_z=10.0, sigma_dl=63.0, pixel=2.0, n_y=400, n
     (dict(n_y=40000), jpet.JPET_EDOMAIN),
     (dict(pixel=2.25), jpet.JPET_EDOMAIN),          # grid reaches |y| >= R
     (dict(kernel_variant=2), jpet.JPET_EDOMAIN),
-    (dict(gamma=0.001), jpet.JPET_ENOTSUP),
+    (dict(gamma=0.001), jpet.JPET_OK),               # C^-1 positive definite: 2 gamma^2 < u w
+    (dict(gamma=-0.001), jpet.JPET_OK),
+    (dict(gamma=0.002), jpet.JPET_EDOMAIN),
+    (dict(gamma=float("nan")), jpet.JPET_EDOMAIN),
 ])
 def test_geometry_validation(lib, over, code):
     g = jpet.geometry(**{**GOOD, **over})

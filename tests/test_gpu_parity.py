@@ -303,6 +303,29 @@ def test_loglik_sigma_gradient_matches_gpu_finite_differences(tiny):
     assert base[2] == pytest.approx(fd_d, rel=1e-3)
 
 
+@pytest.mark.parametrize("gfrac", [0.5, -0.8])
+def test_offdiagonal_cinv_mlem_and_loglik(tiny, gfrac):
+    """gamma != 0 (Eq. 12): one MLEM step and the log-likelihood with gradients against the oracle."""
+    w, ev_np, ev = tiny
+    gam = gfrac * math.sqrt(1 / w.sigma_z ** 2 / w.sigma_dl ** 2 / 2)
+    g, go = geoms(w, gamma=gam)
+    so = oracle.sensitivity(go)
+    rho_o, _ = oracle.mlem(go, ev_np, oracle.initial_image(so), 2, s=so)
+    s = jpet.sensitivity(g)
+    rho = torch.from_numpy(rho_o.astype(np.float32)).to(DEV)
+    want, _ = oracle.mlem(go, ev_np, rho.double().cpu().numpy(), 1, s=so)
+    jpet.mlem_iterate(g, ev, rho, 1, s=s)
+    assert rel_l2(rho.cpu().numpy(), want) <= 1e-4
+    r2 = torch.from_numpy(rho_o.astype(np.float32)).to(DEV)
+    res = jpet.loglik_grad(g, ev, r2, s=s)
+    l, dz, dd, gr, _ = oracle.loglik_grad(go, ev_np, r2.double().cpu().numpy(), s=so)
+    v = res.value.cpu().numpy()
+    assert v[0] == pytest.approx(l, rel=1e-6)
+    assert v[1] == pytest.approx(dz, rel=1e-3)
+    assert v[2] == pytest.approx(dd, rel=1e-3)
+    assert rel_l2(res.grad_rho.cpu().numpy(), gr) <= 1e-4
+
+
 def test_loglik_zero_denominator_is_minus_infinity(tiny):
     w, ev_np, ev = tiny
     g, _ = geoms(w)

@@ -241,6 +241,38 @@ def test_kernel_is_the_second_order_laplace_form(variant):
             assert P[0] == pytest.approx(want, rel=1e-8)
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("gfrac", [0.4, -0.7])
+def test_kernel_with_offdiagonal_cinv_is_the_laplace_form(variant, gfrac):
+    """The same exact second-order Laplace form with the full C^-1 of Eq. 12,
+    [[u, 0, g], [0, u, -g], [g, -g, w]], g = gfrac sqrt(u w / 2) (inside the positive-definite
+    range); the oracle's kernel must follow the off-diagonal terms through kappa, b C^-1 a and the
+    determinant, and its ellipse test (b C^-1 b) must not change."""
+    rng = np.random.default_rng(13)
+    for sz, sdl in [(10.0, 63.0), (5.0, 30.0)]:
+        u, w = 1 / sz ** 2, 1 / sdl ** 2
+        gam = gfrac * math.sqrt(u * w / 2)
+        g = geom(sz, sdl, variant=variant, gamma=gam)
+        Cinv = np.array([[u, 0.0, gam], [0.0, u, -gam], [gam, -gam, w]])
+        for _ in range(40):
+            y, z = rng.uniform(-300, 300), rng.uniform(-200, 200)
+            th = rng.uniform(-0.5, 0.5)
+            ev = forward_vec(y, z, th) + rng.normal(size=3) * [sz, sz, sdl]
+            th_t = math.atan((ev[0] - ev[1]) / (2 * R))
+            f0, f1, f2 = taylor(lambda x: forward_vec(y, z, x), th_t, 2)
+            if variant == 0:
+                f1 = f1 * np.array([1.0, 1.0, 0.5])
+            r0 = f0 - ev
+            g0 = -0.5 * r0 @ Cinv @ r0
+            g1 = -(f1 @ Cinv @ r0)
+            g2 = -0.5 * (f1 @ Cinv @ f1 + 2 * f2 @ Cinv @ r0)
+            norm = math.sqrt(np.linalg.det(Cinv)) / (2 * math.pi) ** 1.5
+            want = norm * math.exp(g0 - g1 * g1 / (4 * g2)) * math.sqrt(math.pi / -g2)
+            P, q = oracle.kernel_points(g, ev, y, z)
+            assert q[0] == pytest.approx(-2 * g0, rel=1e-9, abs=1e-9)
+            assert P[0] == pytest.approx(want, rel=1e-8)
+
+
 @pytest.mark.parametrize("y,z", [(100.0, 37.0), (-150.0, 120.0), (60.0, -200.0)])
 def test_kernel_integrates_to_pi_times_sensitivity(y, z):
     """3-D quadrature over measured events on the strips: int P de = pi s(y, z)."""
@@ -388,15 +420,15 @@ def test_loglik_zero_denominator_is_minus_infinity():
 # gradient: central finite differences with the ellipse mask held fixed
 
 
-@pytest.mark.parametrize("variant", [0, 1])
-def test_sigma_gradient_matches_finite_differences(tiny, variant):
+@pytest.mark.parametrize("variant,gamma", [(0, 0.0), (1, 0.0), (0, 5e-4)])
+def test_sigma_gradient_matches_finite_differences(tiny, variant, gamma):
     g0, ev, s = tiny
     rho = oracle.initial_image(s)
     rho, _ = oracle.mlem(g0, ev, rho, 2, s=s)
     sz, sdl = g0.sigma_z, g0.sigma_dl
 
     def ll(a, b):
-        g = oracle.geometry(g0.R, g0.L, a, b, g0.pixel, g0.n_y, g0.n_z, kernel_variant=variant)
+        g = oracle.geometry(g0.R, g0.L, a, b, g0.pixel, g0.n_y, g0.n_z, kernel_variant=variant, gamma=gamma)
         return oracle.loglik_grad(g, ev, rho, s=s, sigma_mask=[sz, sdl], want_grad_rho=False)
 
     base = ll(sz, sdl)
