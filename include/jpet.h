@@ -118,6 +118,13 @@ int jpet_abi_version(void);
  *   s_out: device float [n_y * n_z], written entirely. */
 int jpet_sensitivity(const jpet_geometry* g, float* s_out, void* stream);
 
+/* Direct-reconstruction image (Eq. 2): for every valid event (finite, |z_u| and |z_d| <= L/2) the
+ * point (y~, z~) of Eq. 2 in double precision, counted in the pixel that contains it (pixel index
+ * floor(y~ / pixel + n_y / 2), likewise for z); points outside the grid are not counted.  A
+ * diagnostic image and a possible MLEM starting image.
+ *   events: device float [n][3]; img: device float [n_y*n_z], overwritten with the counts. */
+int jpet_direct_image(const jpet_geometry* g, const float* events, int64_t n, float* img, void* stream);
+
 /* Bytes of workspace that jpet_mlem_prepare / jpet_mlem_iterate / jpet_mlem_backproject need for
  * n_events events on this geometry (host output *bytes).  The workspace is any device
  * allocation of at least that size, aligned to 256 bytes. */

@@ -8,6 +8,8 @@ The names describe the workloads by what they are:
                 sigma_dl in 40..90, log-uniform 50k..2M events, 10 iterations
 * ``grad200``   R=450, L=500, 200x200 px of 2.5 mm, sigma=(10, 63), 1M events
 * ``large1024`` R=450, L=1000, 1024x1024 px of 0.5 mm, sigma=(5, 30), 100M events, 20 iterations
+* ``paper130``  the paper's own setting: R=130, L=300, 4 mm pixels (64x76 px covering the strips),
+                sigma=(10, 40), the Appendix A phantom, 10M events, 10 iterations
 
 Seeds are 1502074780 + workload index; instance m of ``batch64`` uses seed + 1000 m.
 """
@@ -47,6 +49,8 @@ class Workload:
             return ph.c2_phantom()
         if self.phantom_kind == "dense":
             return ph.dense_phantom(self.seed)
+        if self.phantom_kind == "tablea":
+            return ph.table_a_phantom()
         if self.phantom_kind == "random":
             return ph.random_phantom(self.seed)
         raise ValueError(self.phantom_kind)
@@ -74,6 +78,7 @@ WORKLOADS = {
     "grad200": Workload("grad200", 450.0, 500.0, 10.0, 63.0, 2.5, 200, 200, 1_000_000, 5, BASE_SEED + 4, "c2"),
     "large1024": Workload("large1024", 450.0, 1000.0, 5.0, 30.0, 0.5, 1024, 1024, 100_000_000, 20,
                           BASE_SEED + 5, "dense"),
+    "paper130": Workload("paper130", 130.0, 300.0, 10.0, 40.0, 4.0, 64, 76, 10_000_000, 10, BASE_SEED + 6, "tablea"),
 }
 
 

@@ -73,6 +73,8 @@ def lib():
         L.orc_sensitivity.argtypes = [gp, dp]
         L.orc_direct.argtypes = [gp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.orc_direct.restype = None
+        L.orc_direct_image.argtypes = [gp, ctypes.POINTER(ctypes.c_float), ctypes.c_int64, dp]
+        L.orc_direct_image.restype = ctypes.c_int64
         L.orc_box_halfsize.argtypes = [ctypes.c_double] * 4 + [dp]
         L.orc_box_halfsize.restype = None
         L.orc_kernel_points.argtypes = [gp, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, dp, dp]
@@ -128,6 +130,14 @@ def direct(g: Geometry, zu: float, zd: float, dl: float):
     out = np.empty(4)
     lib().orc_direct(ctypes.byref(g), zu, zd, dl, _ptr(out, ctypes.c_double))
     return tuple(out)
+
+
+def direct_image(g: Geometry, events) -> tuple:
+    """(counts image [n_y, n_z] of the events' direct-reconstruction points (Eq. 2), events counted)."""
+    ev = _events(events)
+    out = np.empty((g.n_y, g.n_z), dtype=np.float64)
+    n = lib().orc_direct_image(ctypes.byref(g), _ptr(ev, ctypes.c_float), len(ev), _ptr(out, ctypes.c_double))
+    return out, int(n)
 
 
 def box_halfsize(sigma_z, sigma_dl, tan_t, sec_t):

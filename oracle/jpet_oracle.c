@@ -143,6 +143,28 @@ void orc_direct(const orc_geometry* g, double zu, double zd, double dl, double o
   out[0] = t; out[1] = c; out[2] = y; out[3] = z;
 }
 
+/* Direct-reconstruction image: each valid event (finite, both hits on the strips) counted at the
+ * pixel containing its point (y~, z~) of Eq. 2 (first forms); points outside the grid are not
+ * counted.  The pixel of a coordinate x on a grid of n pixels is floor(x / pixel + n / 2).
+ * out: n_y * n_z doubles, overwritten; returns the number of events counted. */
+int64_t orc_direct_image(const orc_geometry* g, const float* events, int64_t n, double* out) {
+  for (int64_t q = 0; q < (int64_t)g->n_y * g->n_z; ++q) out[q] = 0.0;
+  int64_t counted = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    const float* e = events + 3 * j;
+    if (!isfinite(e[0]) || !isfinite(e[1]) || !isfinite(e[2])) continue;
+    if (fabs((double)e[0]) > 0.5 * g->L || fabs((double)e[1]) > 0.5 * g->L) continue;
+    double o[4];
+    orc_direct(g, (double)e[0], (double)e[1], (double)e[2], o);
+    const double fi = floor(o[2] / g->pixel + 0.5 * g->n_y);
+    const double fk = floor(o[3] / g->pixel + 0.5 * g->n_z);
+    if (fi < 0.0 || fi >= (double)g->n_y || fk < 0.0 || fk >= (double)g->n_z) continue;
+    out[(int64_t)fi * g->n_z + (int64_t)fk] += 1.0;
+    ++counted;
+  }
+  return counted;
+}
+
 static void estimate(const orc_geometry* g, const float* e, orc_estimate* ev) {
   double o[4];
   orc_direct(g, (double)e[0], (double)e[1], (double)e[2], o);

@@ -489,6 +489,16 @@ int jpet_mlem_workspace_size(const jpet_geometry* g, int64_t n_events, size_t* b
   return JPET_OK;
 }
 
+int jpet_direct_image(const jpet_geometry* g, const float* events, int64_t n, float* img, void* stream) {
+  const int rc = check_geometry(g);
+  if (rc) return rc;
+  if (n < 0 || (n > 0 && !events) || !img) return JPET_EINVAL;
+  const hipError_t e =
+      launch_direct_image(make_geo(g, g->sigma_z, g->sigma_dl), g->L, events, n, img, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return JPET_OK;
+}
+
 int jpet_loglik_workspace_size(const jpet_geometry* g, const double* sigma_mask, int64_t n_events, size_t* bytes) {
   int rc = check_geometry(g);
   if (rc) return rc;

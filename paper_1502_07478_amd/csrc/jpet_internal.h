@@ -166,6 +166,7 @@ size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Work
 
 // Kernel launchers (return the hipError_t of the launch).
 hipError_t launch_sensitivity(const Geo& g, float* s, hipStream_t st);
+hipError_t launch_direct_image(const Geo& g, double L, const float* events, int64_t n, float* img, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_prepare(const Geo& g, const Plan& p, const float* events, int64_t n, const Workspace& ws,
                           hipStream_t st);

@@ -36,6 +36,25 @@ __global__ void k_fill_f64(double* p, int64_t n) {
     p[i] = 0.0;
 }
 
+// Direct-reconstruction image: each valid event counted at the pixel containing (y~, z~) of
+// Eq. 2 (first forms, double precision); the image is zeroed by the caller.
+__global__ void __launch_bounds__(256) k_direct_image(Geo g, double L, const float* __restrict__ events, int64_t n,
+                                                      float* __restrict__ img) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const float zu = events[3 * j], zd = events[3 * j + 1], dl = events[3 * j + 2];
+    if (!isfinite(zu) || !isfinite(zd) || !isfinite(dl)) continue;
+    if (fabs((double)zu) > 0.5 * L || fabs((double)zd) > 0.5 * L) continue;
+    const double t = ((double)zu - (double)zd) / (2.0 * g.R);
+    const double c = sqrt(1.0 + t * t);
+    const double y = -0.5 * (double)dl / c;
+    const double z = 0.5 * ((double)zu + (double)zd + 2.0 * y * t);
+    const double fi = floor(y / g.pixel + 0.5 * (double)g.n_y);
+    const double fk = floor(z / g.pixel + 0.5 * (double)g.n_z);
+    if (fi < 0.0 || fi >= (double)g.n_y || fk < 0.0 || fk >= (double)g.n_z) continue;
+    atomicAdd(&img[(int64_t)fi * g.n_z + (int64_t)fk], 1.0f);
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // log-likelihood and gradient
 
@@ -231,6 +250,13 @@ int grid_for(int64_t n, int block, int cap = 65536) {
 hipError_t launch_sensitivity(const Geo& g, float* s, hipStream_t st) {
   const int64_t npix = (int64_t)g.n_y * g.n_z;
   hipLaunchKernelGGL(k_sensitivity, dim3(grid_for(npix, 256)), dim3(256), 0, st, g, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_image(const Geo& g, double L, const float* events, int64_t n, float* img, hipStream_t st) {
+  const int64_t npix = (int64_t)g.n_y * g.n_z;
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(npix, 256)), dim3(256), 0, st, img, npix);
+  if (n > 0) hipLaunchKernelGGL(k_direct_image, dim3(grid_for(n, 256)), dim3(256), 0, st, g, L, events, n, img);
   return hipGetLastError();
 }
 

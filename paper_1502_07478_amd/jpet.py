@@ -85,6 +85,7 @@ def _lib():
         L.jpet_last_hip_error.argtypes = []
         L.jpet_abi_version.argtypes = []
         L.jpet_sensitivity.argtypes = [gp, vp, vp]
+        L.jpet_direct_image.argtypes = [gp, vp, i64, vp, vp]
         L.jpet_mlem_workspace_size.argtypes = [gp, i64, ctypes.POINTER(sz)]
         L.jpet_mlem_prepare.argtypes = [gp, vp, i64, vp, sz, vp]
         L.jpet_mlem_iterate.argtypes = [gp, vp, i64, vp, vp, i32, vp, sz, u32, sp, vp]
@@ -151,6 +152,15 @@ def profile_read():
 def sensitivity(g: Geometry, device=None, stream=None) -> torch.Tensor:
     out = torch.empty(g.shape, dtype=torch.float32, device=device or "cuda")
     _check(_lib().jpet_sensitivity(ctypes.byref(g), _ptr(out), _stream(stream)), "jpet_sensitivity")
+    return out
+
+
+def direct_image(g: Geometry, events: torch.Tensor, stream=None) -> torch.Tensor:
+    """Counts of the events' direct-reconstruction points (Eq. 2) per pixel (jpet_direct_image)."""
+    _events(events)
+    out = torch.empty(g.shape, dtype=torch.float32, device=events.device)
+    _check(_lib().jpet_direct_image(ctypes.byref(g), _ptr(events), events.shape[0], _ptr(out), _stream(stream)),
+           "jpet_direct_image")
     return out
 
 

@@ -106,6 +106,10 @@ def test_entry_points_reject_bad_arguments_before_any_device_work(lib):
     bad_mask = (ctypes.c_double * 2)(0.0, 63.0)
     assert lib.jpet_loglik_grad(gp, bad_mask, fake, 5, None, fake, fake, None, None, aligned_ws, 1 << 40, 0, None,
                                 None) == jpet.JPET_EDOMAIN
+    # direct image: NULL image, negative count, NULL events with n > 0
+    assert lib.jpet_direct_image(gp, fake, 5, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_direct_image(gp, fake, -1, fake, None) == jpet.JPET_EINVAL
+    assert lib.jpet_direct_image(gp, None, 5, fake, None) == jpet.JPET_EINVAL
     # log-likelihood workspace size: NULL output, negative count, bad mask
     b = ctypes.c_size_t(0)
     assert lib.jpet_loglik_workspace_size(gp, None, 5, None) == jpet.JPET_EINVAL

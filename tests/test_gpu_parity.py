@@ -99,6 +99,29 @@ def test_prepared_workspace_reuse_gives_same_result(tiny):
     assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-6
 
 
+@pytest.mark.parametrize("name", ["tiny", "prod400"])
+def test_direct_image_is_bit_exact(name, tiny, prod):
+    """Integer counts per pixel: identical to the oracle's."""
+    w, ev_np, ev = tiny if name == "tiny" else prod
+    g, go = geoms(w)
+    got = jpet.direct_image(g, ev).cpu().numpy()
+    want, counted = oracle.direct_image(go, ev_np)
+    np.testing.assert_array_equal(got.astype(np.float64), want)
+    assert int(got.sum()) == counted
+
+
+def test_paper_setting_matches_oracle():
+    """The paper's own setting (R=130 mm, L=300 mm, 4 mm pixels, sigma=(10, 40), Appendix A
+    phantom): the first 30k events, two iterations from rho^0."""
+    w = get_workload("paper130")
+    g, go = geoms(w)
+    ev_np = w.events(30_000)
+    so = oracle.sensitivity(go)
+    got, want, st, sto = run_both(g, go, ev_np, oracle.initial_image(so), n_iter=2)
+    assert st["n_pairs"] == sto["n_pairs"] and st["n_valid"] == sto["n_valid"]
+    assert rel_l2(got, want) <= 1e-4
+
+
 def test_count_conservation_gpu(tiny):
     w, _, ev = tiny
     g, _ = geoms(w)

@@ -417,6 +417,35 @@ def test_loglik_zero_denominator_is_minus_infinity():
 
 
 # --------------------------------------------------------------------------------------------
+# direct-reconstruction image: exact events of known points land in the points' pixels
+
+
+def test_direct_image_counts_points_of_exact_events():
+    """Noise-free events of points placed inside known pixels (Eq. 1 forward model, stored in
+    float32) must be counted in exactly those pixels; invalid events and points beyond the grid
+    are not counted."""
+    g = geom(10.0, 63.0, pixel=4.0, n=64, n_z=80)
+    rng = np.random.default_rng(21)
+    want = np.zeros((g.n_y, g.n_z))
+    rows = []
+    while len(rows) < 3000:
+        i, k = rng.integers(0, g.n_y), rng.integers(0, g.n_z)
+        y = (i + 0.5 - g.n_y / 2 + rng.uniform(-0.4, 0.4)) * g.pixel
+        z = (k + 0.5 - g.n_z / 2 + rng.uniform(-0.4, 0.4)) * g.pixel
+        th = rng.uniform(-0.6, 0.6)
+        zu, zd, dl = forward_eq1(y, z, th)
+        if abs(zu) > L / 2 or abs(zd) > L / 2:
+            continue
+        rows.append((zu, zd, dl))
+        want[i, k] += 1
+    extra = [(np.nan, 0.0, 0.0), (L, 0.0, 0.0), (0.0, 0.0, 2 * 1e4)]  # non-finite, off strip, y beyond R
+    ev = np.array(rows + extra, dtype=np.float32)
+    img, counted = oracle.direct_image(g, ev)
+    assert counted == len(rows)
+    np.testing.assert_array_equal(img, want)
+
+
+# --------------------------------------------------------------------------------------------
 # gradient: central finite differences with the ellipse mask held fixed
 
 
