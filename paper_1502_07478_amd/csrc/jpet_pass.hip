@@ -48,12 +48,13 @@ template <int MAXLEN, bool GUARD>
 __device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __restrict__ rho_s, int base, int pitch,
                                        int len, int wmin, int wl, float (&m)[MAXLEN], bool* bad) {
   float D = 0.0f;
+  const float* const rr = rho_s + base;  // the row's first pixel
 #pragma unroll
   for (int j0 = 0; j0 < MAXLEN; j0 += kChunk) {
     if (j0 < wl) {  // wavefront-uniform
       float r[kChunk];
 #pragma unroll
-      for (int jj = 0; jj < kChunk; ++jj) r[jj] = rho_s[base + (j0 + jj) * pitch];
+      for (int jj = 0; jj < kChunk; ++jj) r[jj] = rr[(j0 + jj) * pitch];
       if (!GUARD && j0 + kChunk <= wmin) {  // wavefront-uniform: every active lane's row is longer
 #pragma unroll
         for (int jj = 0; jj < kChunk; ++jj) {
@@ -104,13 +105,16 @@ __device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __
 template <int MAXLEN, bool PRESCALE, typename AccT>
 __device__ __forceinline__ void pass2(const float (&m)[MAXLEN], float sc, int base, int pitch, int len, int wmin,
                                       int wl, AccT* __restrict__ acc_s) {
+  // the row's first accumulator, formed once (the per-pixel offsets are then immediates when the
+  // pitch is a compile-time constant)
+  AccT* const a = acc_s + base;
 #pragma unroll
   for (int j = 0; j < MAXLEN; ++j) {
     const float x = PRESCALE ? m[j] * 18446744073709551616.0f : m[j];
     if (j < wmin) {  // wavefront-uniform
-      atomicAdd(&acc_s[base + j * pitch], (AccT)(unsigned)fmaf(x, sc, 0.5f));
+      atomicAdd(&a[j * pitch], (AccT)(unsigned)fmaf(x, sc, 0.5f));
     } else if (j < wl && j < len) {
-      atomicAdd(&acc_s[base + j * pitch], (AccT)(unsigned)fmaf(x, sc, 0.5f));
+      atomicAdd(&a[j * pitch], (AccT)(unsigned)fmaf(x, sc, 0.5f));
     }
   }
 }
@@ -186,12 +190,13 @@ __device__ __forceinline__ void pass1g(const RowF& rk, const RowD& rd, float qa,
 template <int MAXLEN>
 __device__ __forceinline__ void pass2g(const float (&m)[MAXLEN], float invD, int base, int pitch, int len, int wmin,
                                        int wl, double* __restrict__ B_s) {
+  double* const b = B_s + base;
 #pragma unroll
   for (int j = 0; j < MAXLEN; ++j) {
     if (j < wmin) {  // wavefront-uniform
-      unsafeAtomicAdd(&B_s[base + j * pitch], (double)(m[j] * invD));
+      unsafeAtomicAdd(&b[j * pitch], (double)(m[j] * invD));
     } else if (j < wl && j < len) {
-      unsafeAtomicAdd(&B_s[base + j * pitch], (double)(m[j] * invD));
+      unsafeAtomicAdd(&b[j * pitch], (double)(m[j] * invD));
     }
   }
 }
