@@ -100,21 +100,32 @@ __device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __
   return D;
 }
 
-// Pass 2 along one row: m sc rounded into the 64-bit accumulators.  Below wmin every lane adds
-// (idle lanes and lanes with D = 0 add 0 at a valid address); above it the row end masks.
+// Pass 2 along one row: m sc rounded into the fixed-point accumulators.  In chunks below wmin
+// every lane adds (idle lanes and lanes with D = 0 add 0 at a valid address) with no per-pixel
+// test; past it the row end masks.
 template <int MAXLEN, bool PRESCALE, typename AccT>
 __device__ __forceinline__ void pass2(const float (&m)[MAXLEN], float sc, int base, int pitch, int len, int wmin,
                                       int wl, AccT* __restrict__ acc_s) {
   // the row's first accumulator, formed once (the per-pixel offsets are then immediates when the
   // pitch is a compile-time constant)
   AccT* const a = acc_s + base;
+  // chunks below wmin need no row-end test; past it each row's end masks
 #pragma unroll
-  for (int j = 0; j < MAXLEN; ++j) {
-    const float x = PRESCALE ? m[j] * 18446744073709551616.0f : m[j];
-    if (j < wmin) {  // wavefront-uniform
-      atomicAdd(&a[j * pitch], (AccT)(unsigned)fmaf(x, sc, 0.5f));
-    } else if (j < wl && j < len) {
-      atomicAdd(&a[j * pitch], (AccT)(unsigned)fmaf(x, sc, 0.5f));
+  for (int j0 = 0; j0 < MAXLEN; j0 += kChunk) {
+    if (j0 + kChunk <= wmin) {  // wavefront-uniform
+#pragma unroll
+      for (int jj = 0; jj < kChunk; ++jj) {
+        const int j = j0 + jj;
+        const float x = PRESCALE ? m[j] * 18446744073709551616.0f : m[j];
+        atomicAdd(&a[j * pitch], (AccT)(unsigned)fmaf(x, sc, 0.5f));
+      }
+    } else if (j0 < wl) {  // wavefront-uniform
+#pragma unroll
+      for (int jj = 0; jj < kChunk; ++jj) {
+        const int j = j0 + jj;
+        const float x = PRESCALE ? m[j] * 18446744073709551616.0f : m[j];
+        if (j < len) atomicAdd(&a[j * pitch], (AccT)(unsigned)fmaf(x, sc, 0.5f));
+      }
     }
   }
 }
@@ -192,11 +203,15 @@ __device__ __forceinline__ void pass2g(const float (&m)[MAXLEN], float invD, int
                                        int wl, double* __restrict__ B_s) {
   double* const b = B_s + base;
 #pragma unroll
-  for (int j = 0; j < MAXLEN; ++j) {
-    if (j < wmin) {  // wavefront-uniform
-      unsafeAtomicAdd(&b[j * pitch], (double)(m[j] * invD));
-    } else if (j < wl && j < len) {
-      unsafeAtomicAdd(&b[j * pitch], (double)(m[j] * invD));
+  for (int j0 = 0; j0 < MAXLEN; j0 += kChunk) {
+    if (j0 + kChunk <= wmin) {  // wavefront-uniform
+#pragma unroll
+      for (int jj = 0; jj < kChunk; ++jj) unsafeAtomicAdd(&b[(j0 + jj) * pitch], (double)(m[j0 + jj] * invD));
+    } else if (j0 < wl) {  // wavefront-uniform
+#pragma unroll
+      for (int jj = 0; jj < kChunk; ++jj) {
+        if (j0 + jj < len) unsafeAtomicAdd(&b[(j0 + jj) * pitch], (double)(m[j0 + jj] * invD));
+      }
     }
   }
 }
