@@ -10,6 +10,8 @@ The names describe the workloads by what they are:
 * ``large1024`` R=450, L=1000, 1024x1024 px of 0.5 mm, sigma=(5, 30), 100M events, 20 iterations
 * ``paper130``  the paper's own setting: R=130, L=300, 4 mm pixels (64x76 px covering the strips),
                 sigma=(10, 40), the Appendix A phantom, 10M events, 10 iterations
+* ``edge400``   prod400 with a position-dependent sigma_z: 10 mm at the strip centre rising by 10%
+                towards the ends (sigma_z_edge = 0.1), 10M events, 10 iterations
 
 Seeds are 1502074780 + workload index; instance m of ``batch64`` uses seed + 1000 m.
 """
@@ -41,6 +43,7 @@ class Workload:
     n_iter: int
     seed: int
     phantom_kind: str
+    sigma_z_edge: float = 0.0  # relative rise of sigma_z from the strip centre to its ends
 
     def phantom(self) -> ph.Phantom:
         if self.phantom_kind == "c1":
@@ -60,11 +63,13 @@ class Workload:
         a worker process of a pool)."""
         n = self.n_events if n is None else n
         return simulate_events(self.phantom(), self.R, self.L, self.sigma_z, self.sigma_dl, n,
-                               self.seed + seed_offset, workers=workers)
+                               self.seed + seed_offset, workers=workers, sigma_z_edge=self.sigma_z_edge)
 
     def geometry(self, **over) -> dict:
         g = dict(R=self.R, L=self.L, sigma_z=self.sigma_z, sigma_dl=self.sigma_dl,
                  pixel=self.pixel, n_y=self.n_y, n_z=self.n_z)
+        if self.sigma_z_edge:
+            g["sigma_z_edge"] = self.sigma_z_edge
         g.update(over)
         return g
 
@@ -79,6 +84,8 @@ WORKLOADS = {
     "large1024": Workload("large1024", 450.0, 1000.0, 5.0, 30.0, 0.5, 1024, 1024, 100_000_000, 20,
                           BASE_SEED + 5, "dense"),
     "paper130": Workload("paper130", 130.0, 300.0, 10.0, 40.0, 4.0, 64, 76, 10_000_000, 10, BASE_SEED + 6, "tablea"),
+    "edge400": Workload("edge400", 450.0, 500.0, 10.0, 63.0, 2.0, 400, 400, 10_000_000, 10, BASE_SEED + 7, "c2",
+                        sigma_z_edge=0.1),
 }
 
 

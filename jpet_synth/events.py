@@ -13,7 +13,10 @@ length L along z.  For each accepted emission:
 4. the event is detected only when both hits lie on the strips (|z| <= L/2),
    so detected events are distributed as sensitivity x activity;
 5. Gaussian noise N(0, sigma_z^2) is added to z_u and z_d and N(0, sigma_dl^2)
-   to dl; events whose measured z_u or z_d leave the strips are rejected.
+   to dl; events whose measured z_u or z_d leave the strips are rejected.  With
+   sigma_z_edge > 0 the z noise of a hit at z has the standard deviation
+   sigma_z (1 + sigma_z_edge (2z/L)^2) instead: lowest at the strip centre and
+   higher by the fraction sigma_z_edge at its ends.
 
 Events are returned as float32 ``[n, 3]`` rows (z_u, z_d, dl) in mm.
 """
@@ -66,7 +69,7 @@ _BLOCK = 1 << 20
 
 
 def _simulate_block(args) -> np.ndarray:
-    phantom, R, L, sigma_z, sigma_dl, n, seed, block = args
+    phantom, R, L, sigma_z, sigma_dl, n, seed, block, sigma_z_edge = args
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, block])))
     boxes, weights = _proposal(phantom, R)
     act_of = [e.activity for e in phantom.ellipses]
@@ -82,8 +85,12 @@ def _simulate_block(args) -> np.ndarray:
         z, y, zu, zd = z[hit], y[hit], zu[hit], zd[hit]
         dl = np.sqrt((R - y) ** 2 + (zu - z) ** 2) - np.sqrt((R + y) ** 2 + (zd - z) ** 2)
         nz = rng.normal(0.0, 1.0, (z.size, 3))
-        mzu = zu + sigma_z * nz[:, 0]
-        mzd = zd + sigma_z * nz[:, 1]
+        if sigma_z_edge:
+            mzu = zu + sigma_z * (1.0 + sigma_z_edge * (zu / half) ** 2) * nz[:, 0]
+            mzd = zd + sigma_z * (1.0 + sigma_z_edge * (zd / half) ** 2) * nz[:, 1]
+        else:
+            mzu = zu + sigma_z * nz[:, 0]
+            mzd = zd + sigma_z * nz[:, 1]
         mdl = dl + sigma_dl * nz[:, 2]
         ok = (np.abs(mzu) <= half) & (np.abs(mzd) <= half)
         take = min(int(ok.sum()), n - filled)
@@ -96,7 +103,7 @@ def _simulate_block(args) -> np.ndarray:
 
 
 def simulate_events(phantom: Phantom, R: float, L: float, sigma_z: float, sigma_dl: float,
-                    n: int, seed: int, workers: int | None = None) -> np.ndarray:
+                    n: int, seed: int, workers: int | None = None, sigma_z_edge: float = 0.0) -> np.ndarray:
     """n events; block b of 2^20 events draws from its own stream seeded by (seed, b).
 
     The result is a pure function of (phantom, geometry, resolution, seed) and the first m
@@ -104,7 +111,8 @@ def simulate_events(phantom: Phantom, R: float, L: float, sigma_z: float, sigma_
     number of worker processes.
     """
     nblocks = (n + _BLOCK - 1) // _BLOCK
-    jobs = [(phantom, R, L, sigma_z, sigma_dl, min(_BLOCK, n - b * _BLOCK), seed, b) for b in range(nblocks)]
+    jobs = [(phantom, R, L, sigma_z, sigma_dl, min(_BLOCK, n - b * _BLOCK), seed, b, sigma_z_edge)
+            for b in range(nblocks)]
     if workers is None:
         workers = min(nblocks, 8, os.cpu_count() or 1)
     if workers <= 1 or nblocks <= 1:

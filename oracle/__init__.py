@@ -26,7 +26,7 @@ class Geometry(ctypes.Structure):
         ("R", ctypes.c_double), ("L", ctypes.c_double), ("sigma_z", ctypes.c_double),
         ("sigma_dl", ctypes.c_double), ("gamma", ctypes.c_double), ("pixel", ctypes.c_double),
         ("n_y", ctypes.c_int32), ("n_z", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("sigma_z_edge", ctypes.c_double),
     ]
 
 
@@ -77,6 +77,8 @@ def lib():
         L.orc_direct_image.restype = ctypes.c_int64
         L.orc_box_halfsize.argtypes = [ctypes.c_double] * 4 + [dp]
         L.orc_box_halfsize.restype = None
+        L.orc_sigma_z_factor.argtypes = [gp, ctypes.c_double, ctypes.c_double]
+        L.orc_sigma_z_factor.restype = ctypes.c_double
         L.orc_kernel_points.argtypes = [gp, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, dp, dp]
         L.orc_event_pixels.argtypes = [gp, dp, fp, ctypes.c_int64, i64p, dp]
         L.orc_event_pixels.restype = ctypes.c_int64
@@ -88,8 +90,14 @@ def lib():
     return _lib
 
 
-def geometry(R, L, sigma_z, sigma_dl, pixel, n_y, n_z, kernel_variant=0, gamma=0.0) -> Geometry:
-    return Geometry(R, L, sigma_z, sigma_dl, gamma, pixel, n_y, n_z, kernel_variant, 0)
+def geometry(R, L, sigma_z, sigma_dl, pixel, n_y, n_z, kernel_variant=0, gamma=0.0,
+             sigma_z_edge=0.0) -> Geometry:
+    return Geometry(R, L, sigma_z, sigma_dl, gamma, pixel, n_y, n_z, kernel_variant, 0, sigma_z_edge)
+
+
+def sigma_z_factor(g: Geometry, zu: float, zd: float) -> float:
+    """The event's sigma_z over the geometry's (position-dependent resolution)."""
+    return lib().orc_sigma_z_factor(ctypes.byref(g), zu, zd)
 
 
 def _ptr(a, ctype):

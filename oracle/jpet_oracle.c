@@ -49,6 +49,16 @@
  *       events (P is pi times a probability density, as its integral over all
  *       detectable events is pi s).  Its sigma-gradient holds the ellipse
  *       mask fixed (the mask may be evaluated at separate sigmas).
+ *   R13 sigma_z depending on the measured hit positions (Sec. 3, after Eq. 12:
+ *       weak, about 10% from the strip centre, lowest, to its ends, highest; no
+ *       functional form is given).  Read as one sigma_z per event, entering both
+ *       z slots of C^-1 as in the printed matrix:
+ *         sigma_z(e) = sigma_z (1 + sigma_z_edge * zeta),
+ *         zeta = ((2 z_u / L)^2 + (2 z_d / L)^2) / 2  in [0, 1] for valid events,
+ *       i.e. the mean of a quadratic profile over the two hits.  The event's
+ *       3-sigma ellipse and kernel both use it; sigma_z_edge = 0 is the
+ *       constant-resolution method.  The log-likelihood is defined here for
+ *       sigma_z_edge = 0 only.
  */
 #include <math.h>
 #include <stdint.h>
@@ -70,6 +80,7 @@ typedef struct {
   int32_t n_z;     /* columns (z) */
   int32_t kernel_variant; /* R3: 0 as printed, 1 doubled a_3 */
   int32_t reserved;
+  double sigma_z_edge;     /* R13: relative rise of sigma_z at the strip ends, in [0, 1] */
 } orc_geometry;
 
 typedef struct {
@@ -98,6 +109,7 @@ int orc_check_geometry(const orc_geometry* g) {
   if (g->n_y <= 0 || g->n_z <= 0) return ORC_EDOMAIN;
   if (0.5 * g->n_y * g->pixel >= g->R) return ORC_EDOMAIN;
   if (g->kernel_variant != 0 && g->kernel_variant != 1) return ORC_EDOMAIN;
+  if (!(g->sigma_z_edge >= 0.0 && g->sigma_z_edge <= 1.0)) return ORC_EDOMAIN;
   return ORC_OK;
 }
 
@@ -169,6 +181,14 @@ static void estimate(const orc_geometry* g, const float* e, orc_estimate* ev) {
   double o[4];
   orc_direct(g, (double)e[0], (double)e[1], (double)e[2], o);
   ev->tan_t = o[0]; ev->sec_t = o[1]; ev->y = o[2]; ev->z = o[3];
+}
+
+/* Reading R13: the event's sigma_z over the geometry's, 1 + sigma_z_edge * zeta with zeta the
+ * mean over the two measured hits of (z / (L/2))^2. */
+double orc_sigma_z_factor(const orc_geometry* g, double zu, double zd) {
+  const double xu = zu / (0.5 * g->L), xd = zd / (0.5 * g->L);
+  const double zeta = 0.5 * (xu * xu + xd * xd);
+  return 1.0 + g->sigma_z_edge * zeta;
 }
 
 /* Appendix B (reading R4).  b C^-1 b written as a quadratic form in (dy, dz) is
@@ -274,12 +294,12 @@ int orc_kernel_points(const orc_geometry* g, const double* events, int64_t n, do
                       double* P_out, double* q_out) {
   int rc = orc_check_geometry(g);
   if (rc) return rc;
-  orc_resolution r;
-  resolution(g, g->sigma_z, g->sigma_dl, &r);
   for (int64_t j = 0; j < n; ++j) {
     double o[4];
     orc_direct(g, events[3 * j], events[3 * j + 1], events[3 * j + 2], o);
     orc_estimate ev = { o[0], o[1], o[2], o[3] };
+    orc_resolution r;
+    resolution(g, g->sigma_z * orc_sigma_z_factor(g, events[3 * j], events[3 * j + 1]), g->sigma_dl, &r);
     orc_kernel_value kv;
     kernel(g, &r, &ev, y, z, &kv);
     if (P_out) P_out[j] = kv.P;
@@ -331,10 +351,10 @@ static void list_free(orc_pixel_list* l) {
   memset(l, 0, sizeof(*l));
 }
 
-/* Pixels of the event's 3-sigma ellipse (mask at (msz, mdl)) with the kernel at the geometry's
- * sigmas, in row-major order inside the bounding box.  Returns 0 and count = 0 for an invalid
- * event (reading R7). */
-static int event_pixels(const orc_geometry* g, double msz, double mdl, const orc_resolution* r,
+/* Pixels of the event's 3-sigma ellipse (mask at (msz, mdl)) with the kernel r, in row-major
+ * order inside the bounding box.  Both sigma_z's are scaled by the event's factor (reading R13;
+ * 1 when sigma_z_edge = 0).  Returns 0 and count = 0 for an invalid event (reading R7). */
+static int event_pixels(const orc_geometry* g, double msz, double mdl, const orc_resolution* r0,
                         const float* e, orc_pixel_list* l) {
   l->count = 0;
   l->kappa_bad = 0;
@@ -342,6 +362,11 @@ static int event_pixels(const orc_geometry* g, double msz, double mdl, const orc
   if (fabs((double)e[0]) > 0.5 * g->L || fabs((double)e[1]) > 0.5 * g->L) return ORC_OK;
   orc_estimate ev;
   estimate(g, e, &ev);
+  const double f = orc_sigma_z_factor(g, (double)e[0], (double)e[1]);
+  msz *= f;
+  orc_resolution rr = *r0;
+  rr.u = r0->u / (f * f);  /* u = sigma_z^-2 */
+  const orc_resolution* r = &rr;
   double h[2];
   orc_box_halfsize(msz, mdl, ev.tan_t, ev.sec_t, h);
   int i0, i1, k0, k1;
@@ -454,6 +479,7 @@ int orc_loglik_grad(const orc_geometry* g, const double* sigma_mask, const float
   int rc = orc_check_geometry(g);
   if (rc) return rc;
   if (!events || !rho || !out3 || n < 0) return ORC_EINVAL;
+  if (g->sigma_z_edge != 0.0) return ORC_EINVAL; /* reading R13: constant resolution only */
   const int64_t npix = (int64_t)g->n_y * g->n_z;
   double msz = sigma_mask ? sigma_mask[0] : g->sigma_z, mdl = sigma_mask ? sigma_mask[1] : g->sigma_dl;
   orc_resolution r;
@@ -536,7 +562,8 @@ int orc_backprojection_at(const orc_geometry* g, const float* events, int64_t n,
     orc_estimate ev;
     estimate(g, e, &ev);
     double h[2];
-    orc_box_halfsize(g->sigma_z, g->sigma_dl, ev.tan_t, ev.sec_t, h);
+    orc_box_halfsize(g->sigma_z * orc_sigma_z_factor(g, (double)e[0], (double)e[1]), g->sigma_dl, ev.tan_t,
+                     ev.sec_t, h);
     int i0, i1, k0, k1;
     index_range(ev.y, h[0], g->pixel, g->n_y, &i0, &i1);
     index_range(ev.z, h[1], g->pixel, g->n_z, &k0, &k1);

@@ -498,3 +498,85 @@ def test_sampled_helpers_agree_with_full_iteration(tiny):
     pix = np.array([32 * 64 + 30, 20 * 64 + 40, 50 * 64 + 10])
     acc = oracle.backprojection_at(g, ev, rho, pix)
     np.testing.assert_allclose(acc / s.ravel()[pix], nxt.ravel()[pix], rtol=1e-12)
+
+
+# --------------------------------------------------------------------------------------------
+# sigma_z depending on the hit positions (Sec. 3 after Eq. 12): one sigma_z per event,
+# sigma_z (1 + edge * zeta) with zeta the mean of (z / (L/2))^2 over the two measured hits
+
+
+def event_sigma_z(sz, edge, zu, zd):
+    return sz * (1.0 + edge * 0.5 * ((zu / (L / 2)) ** 2 + (zd / (L / 2)) ** 2))
+
+
+def test_sigma_z_factor_is_lowest_at_the_centre_and_highest_at_the_ends():
+    g = geom(sigma_z_edge=0.1)
+    assert oracle.sigma_z_factor(g, 0.0, 0.0) == 1.0
+    assert oracle.sigma_z_factor(g, L / 2, -L / 2) == pytest.approx(1.1, rel=1e-15)
+    zs = np.linspace(0.0, L / 2, 11)
+    f = [oracle.sigma_z_factor(g, z, z) for z in zs]
+    assert np.all(np.diff(f) > 0)
+    assert oracle.sigma_z_factor(g, 100.0, -30.0) == oracle.sigma_z_factor(g, -30.0, 100.0)
+    assert oracle.sigma_z_factor(geom(), 200.0, 100.0) == 1.0
+    for bad in (-0.1, 1.5, float("nan")):
+        assert oracle.lib().orc_check_geometry(geom(sigma_z_edge=bad)) == oracle.EDOMAIN
+
+
+@pytest.mark.parametrize("edge", [0.1, 0.4])
+def test_position_dependent_kernel_matches_angular_quadrature(edge):
+    """The kernel of an event is the angular integral of the 3-D Gaussian at that event's sigma_z."""
+    sz, sdl = 10.0, 63.0
+    g = geom(sz, sdl, sigma_z_edge=edge)
+    rng = np.random.default_rng(17)
+    errs = []
+    while len(errs) < 120:
+        y, z = rng.uniform(-200, 200), rng.uniform(-150, 150)
+        th = rng.uniform(-0.5, 0.5)
+        zu, zd, dl = forward_eq1(y, z, th)
+        ev = np.array([zu + rng.normal() * sz, zd + rng.normal() * sz, dl + rng.normal() * sdl])
+        if max(abs(ev[0]), abs(ev[1])) > L / 2:
+            continue
+        P, q = oracle.kernel_points(g, ev, y, z)
+        if q[0] > 9:
+            continue
+        errs.append(P[0] / exact_kernel(ev, y, z, event_sigma_z(sz, edge, ev[0], ev[1]), sdl) - 1)
+    errs = np.abs(np.array(errs))
+    assert np.median(errs) < 2e-3
+    assert np.percentile(errs, 95) < 1.5e-2
+
+
+def test_position_dependent_pixels_are_exactly_the_event_ellipse():
+    """Brute force: the pixel set is {pixel centres with q <= 9} at the event's own sigma_z, and
+    the kernel values equal those of a constant-resolution geometry at that sigma_z."""
+    edge = 0.1
+    g = geom(pixel=2.0, n=400, sigma_z_edge=edge)
+    ev = get_workload("edge400").events(200)
+    n = 400
+    yc = (np.arange(n) + 0.5 - n / 2) * 2.0
+    Y, Z = np.meshgrid(yc, yc, indexing="ij")
+    grew = 0
+    for e in ev[:60]:
+        sz_e = event_sigma_z(10.0, edge, float(e[0]), float(e[1]))
+        t, c, yt, zt = oracle.direct(g, *map(float, e))
+        want = np.nonzero((bcb(Y - yt, Z - zt, t, c, sz_e, 63.0) <= 9.0).ravel())[0]
+        pix, P = oracle.event_pixels(g, e)
+        assert np.array_equal(np.sort(pix), want)
+        p0, P0 = oracle.event_pixels(geom(sz=sz_e, pixel=2.0, n=400), e)
+        assert np.array_equal(pix, p0)
+        np.testing.assert_allclose(P, P0, rtol=1e-12)
+        grew += len(pix) > len(oracle.event_pixels(geom(pixel=2.0, n=400), e)[0])
+    assert grew > 20
+
+
+def test_position_dependent_mlem_conserves_counts():
+    w = get_workload("tiny").replace(sigma_z_edge=0.2)
+    g = oracle.geometry(**w.geometry())
+    ev = w.events(3000)
+    s = oracle.sensitivity(g)
+    rho, st = oracle.mlem(g, ev, oracle.initial_image(s), 2, s=s)
+    assert (s * rho).sum() == pytest.approx(st["n_valid"] - st["n_zero_denominator"], rel=1e-12)
+    rho0, st0 = oracle.mlem(oracle.geometry(**get_workload("tiny").geometry()), ev, oracle.initial_image(s), 2, s=s)
+    assert st["n_pairs"] > st0["n_pairs"]
+    # the log-likelihood is defined for a constant sigma_z only
+    with pytest.raises(ValueError):
+        oracle.loglik_grad(g, ev, rho, s=s)
