@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define JPET_ABI_VERSION 1
+#define JPET_ABI_VERSION 2
 
 enum jpet_status {
   JPET_OK = 0,
@@ -61,8 +61,9 @@ enum jpet_status {
 /* Detector, resolution and pixel grid.  All members are read by value; the struct is
  * host memory.  Domain (else JPET_EDOMAIN): R, L, sigma_z, sigma_dl, pixel finite and > 0;
  * 0 < n_y, n_z <= 32768; n_y * pixel / 2 < R (every pixel centre lies between the strips);
- * kernel_variant in {0, 1}; gamma finite with 2 gamma^2 < sigma_z^-2 sigma_dl^-2 (C^-1 of Eq. 12
- * positive definite). */
+ * kernel_variant in {0, 1}; 0 <= sigma_z_edge <= 1; gamma finite with
+ * 2 gamma^2 < sigma_z,max^-2 sigma_dl^-2, sigma_z,max = sigma_z (1 + sigma_z_edge) (C^-1 of Eq. 12
+ * positive definite for every event). */
 typedef struct jpet_geometry {
   double R;              /* strip half-separation: strips at y = +R and y = -R (Setup, Eq. 1) */
   double L;              /* strip length; strips span z in [-L/2, L/2] (Eq. 4) */
@@ -76,6 +77,12 @@ typedef struct jpet_geometry {
   int32_t kernel_variant;/* third component of a (Eq. 9): 0 as printed, 1 twice that (the
                             exact derivative of dl with respect to the emission angle) */
   int32_t reserved;      /* must be 0 */
+  double sigma_z_edge;   /* sigma_z depending on the hit positions (Sec. 3, after Eq. 12): an event
+                            with measured hits z_u, z_d takes, in both z slots of C^-1 and in its
+                            3-sigma ellipse, sigma_z (1 + sigma_z_edge * zeta) with
+                            zeta = ((2 z_u / L)^2 + (2 z_d / L)^2) / 2, so sigma_z at the strip
+                            centre rising by the fraction sigma_z_edge at its ends; 0: constant.
+                            The log-likelihood entry points take 0 only (else JPET_ENOTSUP). */
 } jpet_geometry;
 
 /* Per-call counters (host memory).  An event is valid when its three numbers are finite,
@@ -99,6 +106,12 @@ typedef struct jpet_stats {
 #define JPET_WS_PREPARED 1u /* the workspace already holds jpet_mlem_prepare's output for
                                exactly this geometry, event array and event count (for
                                jpet_loglik_grad: prepared with the mask's sigmas); skip that step */
+/* Work splits of the event pass for comparison (jpet_mlem_iterate, jpet_mlem_backproject; at most
+ * one of them): one wavefront per event (a lane per ellipse row), or one thread per event, the
+ * granularity of the paper's GPU "thread" variant (Sec. 4, Table 1).  Both read the image and add
+ * to the accumulators in global memory; the result equals the planned pass's to rounding. */
+#define JPET_PASS_WAVE_PER_EVENT 2u
+#define JPET_PASS_THREAD_PER_EVENT 4u
 
 /* Text for a status code (static storage, never NULL). */
 const char* jpet_strerror(int status);
@@ -143,7 +156,8 @@ int jpet_mlem_prepare(const jpet_geometry* g, const float* events, int64_t n, vo
  *           Eq. 5 form in which no sensitivity is applied (s = 1 everywhere)
  *   rho:    device float [n_y*n_z], the current image on entry, the image after n_iter
  *           iterations on return.  rho must be finite and >= 0.  Pixels with s = 0 are set to 0.
- *   n_iter >= 0; flags: 0 or JPET_WS_PREPARED; stats: host, nullable (synchronises if given).
+ *   n_iter >= 0; flags: 0 or JPET_WS_PREPARED, optionally with one of the JPET_PASS_* comparison
+ *   work splits; stats: host, nullable (synchronises if given).
  * One iteration: for every valid event j, D_j = sum_{i in ellipse} P_ji rho_i; for D_j > 0 the
  * values rho_l P_jl / D_j are summed into the new image; then rho_l = sum / s_l (s_l > 0) or 0. */
 int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, const float* s, float* rho,
@@ -185,7 +199,9 @@ int jpet_mlem_update(const jpet_geometry* g, const float* s, uint64_t* acc, floa
  * flags = JPET_WS_PREPARED reuses the preparation of an earlier jpet_loglik_grad call on the same
  * workspace with the same geometry, mask, events and count; it is refused (JPET_EINVAL) when
  * sigma_mask differs from the geometry's sigmas, because the prepared kernel constants belong to
- * the sigmas the workspace was prepared with. */
+ * the sigmas the workspace was prepared with.
+ * Both log-likelihood entry points return JPET_ENOTSUP for a geometry with sigma_z_edge != 0 (the
+ * log-likelihood is defined here for one sigma_z shared by all events). */
 /* Bytes of workspace jpet_loglik_grad needs for n_events events (host output *bytes); the layout
  * follows the mask (sigma_mask as for jpet_loglik_grad, nullable). */
 int jpet_loglik_workspace_size(const jpet_geometry* g, const double* sigma_mask, int64_t n_events, size_t* bytes);

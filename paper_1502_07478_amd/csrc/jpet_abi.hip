@@ -49,9 +49,12 @@ int check_geometry(const jpet_geometry* g) {
   if (!(0.5 * (double)g->n_y * g->pixel < g->R)) return JPET_EDOMAIN;
   if (g->kernel_variant != 0 && g->kernel_variant != 1) return JPET_EDOMAIN;
   if (!isfinite(g->gamma)) return JPET_EDOMAIN;
-  // C^-1 (Eq. 12) must be positive definite: u > 0, w > 0 and u^2 w - 2 u gamma^2 > 0
+  if (!(g->sigma_z_edge >= 0.0 && g->sigma_z_edge <= 1.0)) return JPET_EDOMAIN;
+  // C^-1 (Eq. 12) must be positive definite for every event: u > 0, w > 0 and
+  // u^2 w - 2 u gamma^2 > 0 down to the smallest u, that of the largest sigma_z
   {
-    const double u = 1.0 / (g->sigma_z * g->sigma_z), w = 1.0 / (g->sigma_dl * g->sigma_dl);
+    const double szm = g->sigma_z * (1.0 + g->sigma_z_edge);
+    const double u = 1.0 / (szm * szm), w = 1.0 / (g->sigma_dl * g->sigma_dl);
     if (!(2.0 * g->gamma * g->gamma < u * w)) return JPET_EDOMAIN;
   }
   if (g->reserved != 0) return JPET_EINVAL;
@@ -72,6 +75,7 @@ Geo make_geo(const jpet_geometry* g, double mask_sz, double mask_sdl) {
   o.wm = 1.0 / (mask_sdl * mask_sdl);
   o.fa = g->kernel_variant ? 2.0 : 1.0;
   o.gamma = g->gamma;
+  o.zedge = g->sigma_z_edge;
   {
     const double det = o.u * o.u * o.w - 2.0 * o.u * o.gamma * o.gamma;
     o.cnorm = sqrt(det) / (2.0 * 3.14159265358979323846);
@@ -169,6 +173,7 @@ static void finish_plan(const jpet_geometry* g, int rows_max, int64_t n, Plan& p
 
 Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int force_waves, bool loglik) {
   const bool allow_acc32 = !loglik;
+  msz *= 1.0 + g->sigma_z_edge;  // the largest ellipse: sigma_z at the strip ends
   Plan none;
   memset(&none, 0, sizeof(none));
   none.ntb = 1;
@@ -207,7 +212,11 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
   // plus, at most, one partial item per bin.
   // (the log-likelihood pass, with its derivative terms, keeps 5 / 4 / 4 / 4)
   const int simd_waves = loglik ? (maxlen <= 16 ? 5 : 4) : maxlen <= 16 ? 8 : maxlen <= 32 ? 6 : maxlen <= 48 ? 5 : 4;
-  const size_t kLdsPerCU = 160 * 1024, kStatic = 7 * 1024;
+  // LDS per CU, the passes' static LDS (batch buffers; more in the log-likelihood pass), and the
+  // allocation granule: measured on gfx950, three workgroups of 51,984 bytes each run on one CU
+  // but three of 54,032 bytes do not (the pass then runs 27% slower), so a workgroup's LDS is
+  // counted in whole 2 KB granules.
+  const size_t kLdsPerCU = 160 * 1024, kStatic = loglik ? 8 * 1024 : 7 * 1024, kGranule = 2048;
   const double dts[] = {0.0, 0.4, 0.2, 0.1, 0.05, 0.025};
   const int tiles[] = {32, 24, 16, 12, 8};
   const double pairs_per_event = 3.14159265358979323846 * hy_px * (3.0 * msz / sqrt(2.0) / pix);
@@ -219,7 +228,7 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
     for (int wgs = 1; wgs <= 4; ++wgs) {
       const int occ = wgs * waves / 4;  // resident wavefronts per SIMD
       if (occ > simd_waves) continue;
-      const size_t budget = kLdsPerCU / (size_t)wgs - kStatic;
+      const size_t budget = kLdsPerCU / (size_t)wgs / kGranule * kGranule - kStatic;
       const double occ_factor = pow(4.0 / (double)occ, 0.58) * (waves == 16 ? 1.1 : 1.0);
       for (int acc32 = 0; acc32 <= 1; ++acc32) {
         if (acc32 && !allow_acc32) continue;
@@ -421,11 +430,19 @@ static int timed(F launch, hipStream_t st) {
 }
 
 static int timed_event_pass(const Geo& geo, const Plan& p, int64_t n, const Workspace& w, const float* rho,
-                            hipStream_t st) {
+                            hipStream_t st, int granularity = kPassPlanned) {
   // per-pass counters: zero-denominator events, non-positive kappa pairs, unplaced rows
   hipError_t e = launch_fill_u64(w.cnt + C_ZERO_DEN, 2, st);
   if (e != hipSuccess) return hip_fail(e);
-  return timed([&] { return launch_event_pass(geo, p, n, w, rho, st); }, st);
+  return timed([&] { return launch_event_pass(geo, p, n, w, rho, st, granularity); }, st);
+}
+
+// The pass granularity a flag word asks for; -1 for unknown flags or both comparison flags.
+static int pass_granularity(uint32_t flags) {
+  if (flags & ~(JPET_WS_PREPARED | JPET_PASS_WAVE_PER_EVENT | JPET_PASS_THREAD_PER_EVENT)) return -1;
+  const bool wv = (flags & JPET_PASS_WAVE_PER_EVENT) != 0, th = (flags & JPET_PASS_THREAD_PER_EVENT) != 0;
+  if (wv && th) return -1;
+  return wv ? kPassWavePerEvent : th ? kPassThreadPerEvent : kPassPlanned;
 }
 
 extern "C" {
@@ -503,6 +520,7 @@ int jpet_loglik_workspace_size(const jpet_geometry* g, const double* sigma_mask,
   int rc = check_geometry(g);
   if (rc) return rc;
   if (!bytes || n_events < 0) return JPET_EINVAL;
+  if (g->sigma_z_edge != 0.0) return JPET_ENOTSUP;  // defined for one sigma_z for all events
   double msz = g->sigma_z, mdl = g->sigma_dl;
   if (sigma_mask) {
     msz = sigma_mask[0];
@@ -556,7 +574,8 @@ int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, co
   int rc = check_geometry(g);
   if (rc) return rc;
   if (n < 0 || (n > 0 && !events) || !rho || n_iter < 0) return JPET_EINVAL;
-  if (flags & ~JPET_WS_PREPARED) return JPET_EINVAL;
+  const int gran = pass_granularity(flags);
+  if (gran < 0) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
   Workspace w;
   rc = carve(p, g, n, ws, ws_bytes, &w);
@@ -570,7 +589,7 @@ int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, co
   hipError_t e = launch_fill_u64(w.acc, npix_of(g), st);
   if (e != hipSuccess) return hip_fail(e);
   for (int it = 0; it < n_iter; ++it) {
-    rc = timed_event_pass(geo, p, n, w, rho, st);
+    rc = timed_event_pass(geo, p, n, w, rho, st, gran);
     if (rc) return rc;
     e = launch_update(geo, s, rho, w, st);
     if (e != hipSuccess) return hip_fail(e);
@@ -584,7 +603,8 @@ int jpet_mlem_backproject(const jpet_geometry* g, const float* events, int64_t n
   int rc = check_geometry(g);
   if (rc) return rc;
   if (n < 0 || (n > 0 && !events) || !rho || !acc) return JPET_EINVAL;
-  if (flags & ~JPET_WS_PREPARED) return JPET_EINVAL;
+  const int gran = pass_granularity(flags);
+  if (gran < 0) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
   Workspace w;
   rc = carve(p, g, n, ws, ws_bytes, &w);
@@ -596,7 +616,7 @@ int jpet_mlem_backproject(const jpet_geometry* g, const float* events, int64_t n
     if (rc) return rc;
   }
   w.acc = reinterpret_cast<unsigned long long*>(acc);
-  rc = timed_event_pass(geo, p, n, w, rho, st);
+  rc = timed_event_pass(geo, p, n, w, rho, st, gran);
   if (rc) return rc;
   if (stats) return read_stats(w, n, stats, st);
   return JPET_OK;
@@ -621,6 +641,7 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
   if (rc) return rc;
   if (n < 0 || (n > 0 && !events) || !rho || !out3) return JPET_EINVAL;
   if (flags & ~JPET_WS_PREPARED) return JPET_EINVAL;
+  if (g->sigma_z_edge != 0.0) return JPET_ENOTSUP;  // defined for one sigma_z for all events
   double msz = g->sigma_z, mdl = g->sigma_dl;
   if (sigma_mask) {
     msz = sigma_mask[0];

@@ -70,7 +70,7 @@ __device__ inline double bin_slope(const Plan& p, int b) {
 }
 
 // Pixel columns [klo, khi] of row i inside the 3-sigma ellipse of event e, for the mask
-// resolution (um, wm).  In a row of fixed y the quadratic form b C^-1 b equals
+// resolution (um, wm), um scaled by the event's su (its own sigma_z).  In a row of fixed y the quadratic form b C^-1 b equals
 // 2 um b1^2 + 4 wm c^2 dy^2 with b1 = z - z~ - dy tan (Eq. 10-12), so the ellipse (Sec. 3) is the
 // interval |z - (z~ + dy tan)| <= sqrt((9 - 4 wm c^2 dy^2) / (2 um)).  Double precision, so the
 // pixel set is the one a per-pixel double-precision test b C^-1 b <= 9 selects.
@@ -80,7 +80,7 @@ __device__ inline bool row_interval(const Geo& g, const EventRec& e, int i, int*
   const double c = e.c;
   const double rem = 9.0 - 4.0 * g.wm * c * c * dy * dy;
   if (!(rem >= 0.0)) return false;
-  const double H = sqrt(rem * (0.5 / g.um));
+  const double H = sqrt(rem * (0.5 / (g.um * e.su)));
   const double zc = e.z + e.t * dy;
   double a = ceil((zc - H - g.z0) * g.ipix);
   double b = floor((zc + H - g.z0) * g.ipix);
@@ -111,7 +111,7 @@ __device__ inline RowK row_constants(const Geo& g, const EventRec& e, int i, int
   const double Y = g.y0 + (double)i * g.pixel;
   const double dy = Y - e.y;
   const double t = e.t, c = e.c, c2 = c * c;
-  const double u = g.u, w = g.w, f = g.fa;
+  const double u = g.u * e.su, w = g.w, f = g.fa;  // u: this event's sigma_z^-2
   const double zc = e.z + t * dy;
   const double b10 = g.z0 + (double)klo * g.pixel - zc;
   const double kap_r = 2.0 * u * c2 * c2 * (g.R * g.R + Y * Y) + w * f * f * Y * Y * c2 * t * t +

@@ -19,6 +19,7 @@ struct Geo {
   double cnorm;        // sqrt(det C^-1) / (2 pi), det C^-1 = u^2 w - 2 u gamma^2: P = cnorm P'
   double cu, cw;       // (d det / du) / (2 det) and (d det / dw) / (2 det): the prefactor's share
                        // of d log P / du and d log P / dw
+  double zedge;        // relative rise of sigma_z at the strip ends (per-event sigma_z; 0: none)
   int32_t n_y, n_z;
 };
 
@@ -30,6 +31,8 @@ struct EventRec {
   double c;      // 1 / cos(theta~) = sqrt(1 + t^2)
   double y;      // y~
   double z;      // z~
+  double su;     // this event's u over the geometry's: (sigma_z / sigma_z(e))^2, 1 for a constant
+                 // sigma_z
   int32_t r0;    // first pixel row of the 3-sigma ellipse (App. B), clipped to the grid
   int32_t r1;    // last row; r1 < r0 marks an invalid (dropped) event
   int32_t npix;  // pixel centres inside the ellipse
@@ -40,11 +43,12 @@ struct EventRec {
 // row's y, dy = Y - y~ and b1 = z - z~ - dy tan (Eq. 8-12):
 //   kappa = aC^-1a + 2 oC^-1b = A1 (R^2 + Y^2) + A2 Y^2 + A3 Y dy + KB Y b1
 //   gamma = bC^-1a           = G1 Y dy + GB Y b1
-//   S q   = S bC^-1b         = S 2u b1^2 + Q3s dy^2            (S = log2(e) / 2)
+//   S q   = S bC^-1b         = S2u b1^2 + Q3s dy^2             (S = log2(e) / 2)
+// with u this event's sigma_z^-2.
 struct EvConst {
   float yr, zr;         // y~ and z~ relative to the centre of the bin region's pixel (0, 0)
   int32_t index;        // position of the event in the caller's array
-  int32_t pad0;
+  float S2u;            // S 2u
   float t;              // tan(theta~)
   float A1, A2, A3, KB; // 2u c^4, w fa^2 c^2 t^2, 4 w c^2 (1 + 2t^2), -4 u t c^2
   float G1, GB, Q3s;    // 2 fa w c^2 t, -2 u c^2, S 4 w c^2
@@ -170,8 +174,11 @@ hipError_t launch_direct_image(const Geo& g, double L, const float* events, int6
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_prepare(const Geo& g, const Plan& p, const float* events, int64_t n, const Workspace& ws,
                           hipStream_t st);
+// Work split of the event pass: the plan's (binned when tiled), or for comparison one wavefront
+// per event (the generic pass) or one thread per event.
+constexpr int kPassPlanned = 0, kPassWavePerEvent = 1, kPassThreadPerEvent = 2;
 hipError_t launch_event_pass(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
-                             hipStream_t st);
+                             hipStream_t st, int granularity = kPassPlanned);
 hipError_t launch_update(const Geo& g, const float* s, float* rho, const Workspace& ws, hipStream_t st);
 // batched: table of count instances in device memory; grid = total workgroups of the tiled ones
 hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t st);

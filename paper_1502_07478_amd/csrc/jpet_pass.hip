@@ -34,12 +34,13 @@ struct PassShared {
 // Single-precision kernel constants along one pixel row (Eq. 7-12); j is the pixel's
 // offset in the row:
 //   kappa_j = kap0 + j dkap,  sqrt(S) gamma_j = gs0 + j dgs,  S q_j = (qa j + qb) j + qc
+// (qa = S 2u pixel^2 depends on the event through its sigma_z)
 // and P / (sqrt(det C^-1) / 2 pi) = kappa^-1/2 exp2(S gamma^2 / kappa - S q), S = log2(e) / 2.
 // The off-diagonal gamma of C^-1 enters only kappa and gamma^ through per-row constants: with
 // b1 = b2, the gamma terms of b C^-1 b cancel (so the ellipse does not depend on gamma) while
 // kappa gains -4 gamma R c^3 t (fa y + 2 dy) and gamma^ gains -4 gamma R c^3 dy.
 struct RowF {
-  float kap0, dkap, gs0, dgs, qb, qc;
+  float kap0, dkap, gs0, dgs, qa, qb, qc;
 };
 
 // Pass 1 along one row.  Chunks below the wavefront's shortest row (wmin, uniform) need no row-end
@@ -392,7 +393,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       const int e = (int)((word >> kWordEv) & 31u);
       int base = 0;
       bool safe = true;
-      RowF rk = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 1e30f};  // idle lane: every kernel value is 0
+      RowF rk = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 1e30f};  // idle lane: every kernel value is 0
       RowD rd = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       if (len > 0) {
         const int kl = (int)((word >> kWordCol) & 255u);
@@ -410,8 +411,11 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
         rk.dkap = kb * pixf;
         rk.gs0 = rs * fmaf(gb, b10, fmaf(c.GG, dy, c.G1 * Y * dy));
         rk.dgs = rs * gb * pixf;
-        rk.qb = 2.0f * S2u * b10 * pixf;
-        rk.qc = fmaf(S2u * b10, b10, c.Q3s * dy * dy);
+        // S 2u of this event (its own sigma_z); the log-likelihood mode has one sigma_z for all
+        const float s2u = GRAD ? S2u : c.S2u;
+        rk.qa = s2u * pixf * pixf;
+        rk.qb = 2.0f * s2u * b10 * pixf;
+        rk.qc = fmaf(s2u * b10, b10, c.Q3s * dy * dy);
         if constexpr (GRAD) {
           rd.b10 = b10;
           rd.Kzh0 = 0.5f * iu * fmaf(kb, b10, c.A1 * (R2 + Y * Y));
@@ -438,9 +442,9 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
         }
       } else {
         if (__any(!safe)) {
-          D = pass1<MAXLEN, true>(rk, qa, rho_s, base, pitch, len, wn, wl, m, &bad);
+          D = pass1<MAXLEN, true>(rk, rk.qa, rho_s, base, pitch, len, wn, wl, m, &bad);
         } else {
-          D = pass1<MAXLEN, false>(rk, qa, rho_s, base, pitch, len, wn, wl, m, &bad);
+          D = pass1<MAXLEN, false>(rk, rk.qa, rho_s, base, pitch, len, wn, wl, m, &bad);
         }
       }
       if (bad) atomicAdd(&ps.bad, 1u);
@@ -627,6 +631,48 @@ __global__ void __launch_bounds__(256) k_event_pass_generic(Geo g, int64_t n, co
   }
 }
 
+// Thread-granularity pass (comparison only): one thread per event walks every pixel of its
+// ellipse twice, first for D, then adding the back-projection with global fixed-point atomics.
+// This is the GPU work split the paper measures as its "thread" variant (Sec. 4, Table 1); lanes
+// of a wavefront hold events of different sizes and read unrelated image rows.
+__global__ void __launch_bounds__(256) k_event_pass_thread(Geo g, int64_t n, const EventRec* __restrict__ ev,
+                                                           const float* __restrict__ rho,
+                                                           unsigned long long* __restrict__ acc,
+                                                           unsigned long long* __restrict__ cnt) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const EventRec e = ev[j];
+  if (e.r1 < e.r0) return;
+  bool bad = false;
+  float D = 0.0f;
+  for (int i = e.r0; i <= e.r1; ++i) {
+    int klo, khi;
+    if (!row_interval(g, e, i, &klo, &khi)) continue;
+    double kf, ks;
+    const RowK r = row_constants(g, e, i, klo, &kf, &ks);
+    const float* rr = rho + (int64_t)i * g.n_z;
+    for (int k = klo; k <= khi; ++k) D += kernel_guarded(r, (float)(k - klo), &bad) * rr[k];
+  }
+  if (bad) atomicAdd(&cnt[C_KAPPA_BAD], 1ull);
+  if (!(D > 0.0f)) {
+    atomicAdd(&cnt[C_ZERO_DEN], 1ull);
+    return;
+  }
+  const float sc = (float)(4294967296.0 / (double)D);
+  for (int i = e.r0; i <= e.r1; ++i) {
+    int klo, khi;
+    if (!row_interval(g, e, i, &klo, &khi)) continue;
+    double kf, ks;
+    const RowK r = row_constants(g, e, i, klo, &kf, &ks);
+    const float* rr = rho + (int64_t)i * g.n_z;
+    unsigned long long* aa = acc + (int64_t)i * g.n_z;
+    for (int k = klo; k <= khi; ++k) {
+      const float m = kernel_guarded(r, (float)(k - klo), &bad) * rr[k];
+      if (m > 0.0f) atomicAdd(&aa[k], (unsigned long long)(unsigned)fmaf(m, sc, 0.5f));
+    }
+  }
+}
+
 // rho_l = acc_l 2^-32 / s_l (0 where s_l = 0), or acc_l 2^-32 without sensitivity; acc cleared.
 __global__ void k_update(int64_t npix, const float* __restrict__ s, float* __restrict__ rho,
                          unsigned long long* __restrict__ acc) {
@@ -769,9 +815,14 @@ hipError_t launch_update_batched(const BatchInst* table, int count, int64_t max_
 }
 
 hipError_t launch_event_pass(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
-                             hipStream_t st) {
+                             hipStream_t st, int granularity) {
   if (n <= 0) return hipSuccess;
-  if (p.tiled) {
+  if (granularity == kPassThreadPerEvent) {
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_event_pass_thread, dim3((unsigned)blocks), dim3(256), 0, st, g, n, ws.ev, rho, ws.acc, ws.cnt);
+    return hipGetLastError();
+  }
+  if (p.tiled && granularity == kPassPlanned) {
     const int key = p.maxlen * 100 + p.waves + (p.acc32 ? 10000 : 0);
     switch (key) {
       case 1608: return launch_tiled<16, 8, false>(g, p, ws, rho, st);

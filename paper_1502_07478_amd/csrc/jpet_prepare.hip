@@ -43,6 +43,7 @@ __global__ void __launch_bounds__(256) k_prepare(Geo g, Plan p, const float* __r
     e.npix = 0;
     e.index = (int32_t)j;
     e.t = e.c = e.y = e.z = 0.0;
+    e.su = 1.0;
     uint32_t k = kNoBin;
     const double hl = 0.5 * g.L;
     if (isfinite(zu) && isfinite(zd) && isfinite(dl) && fabs((double)zu) <= hl && fabs((double)zd) <= hl) {
@@ -55,6 +56,13 @@ __global__ void __launch_bounds__(256) k_prepare(Geo g, Plan p, const float* __r
       e.c = c;
       e.y = y;
       e.z = z;
+      // this event's sigma_z: sigma_z (1 + zedge zeta), zeta the mean of (z / (L/2))^2 over the
+      // two hits (Sec. 3 after Eq. 12); u scales by the inverse square
+      {
+        const double xu = (double)zu / hl, xd = (double)zd / hl;
+        const double f = 1.0 + g.zedge * (0.5 * (xu * xu + xd * xd));
+        e.su = 1.0 / (f * f);
+      }
       // rows within the ellipse's half height 1.5 sigma_dl / c (App. B)
       const double hy = 1.5 / (sqrt(g.wm) * c);
       double a = ceil((y - hy - g.y0) * g.ipix);
@@ -236,12 +244,13 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
       const int K = min(mrow, nrows - mrow) >> 4;
       K_s[tid] = K;
       top_s[tid] = mrow - 16 * K;
-      const float t = (float)e.t, c2 = (float)(e.c * e.c), u = (float)g.u, w = (float)g.w, fa = (float)g.fa;
+      const float t = (float)e.t, c2 = (float)(e.c * e.c), u = (float)(g.u * e.su), w = (float)g.w,
+                  fa = (float)g.fa;
       EvConst k;
       k.yr = (float)(e.y - (g.y0 + (double)rbase * g.pixel));
       k.zr = (float)(e.z - (g.z0 + (double)kbase * g.pixel));
       k.index = e.index;
-      k.pad0 = 0;
+      k.S2u = (float)(kHalfLog2e * 2.0 * (g.u * e.su));
       k.t = t;
       k.A1 = 2.0f * u * c2 * c2;
       k.A2 = w * fa * fa * c2 * t * t;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libjpet.so")
 
 JPET_OK, JPET_EINVAL, JPET_EDOMAIN, JPET_EWORKSPACE, JPET_EHIP, JPET_ENOTSUP = 0, -1, -2, -3, -4, -5
 JPET_WS_PREPARED = 1
+JPET_PASS_WAVE_PER_EVENT, JPET_PASS_THREAD_PER_EVENT = 2, 4
 
 
 class JpetError(RuntimeError):
@@ -34,7 +35,7 @@ class Geometry(ctypes.Structure):
         ("R", ctypes.c_double), ("L", ctypes.c_double), ("sigma_z", ctypes.c_double),
         ("sigma_dl", ctypes.c_double), ("gamma", ctypes.c_double), ("pixel", ctypes.c_double),
         ("n_y", ctypes.c_int32), ("n_z", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("sigma_z_edge", ctypes.c_double),
     ]
 
     @property
@@ -110,9 +111,11 @@ def lib():
     return _lib()
 
 
-def geometry(R, L, sigma_z, sigma_dl, pixel, n_y, n_z, kernel_variant=0, gamma=0.0) -> Geometry:
+def geometry(R, L, sigma_z, sigma_dl, pixel, n_y, n_z, kernel_variant=0, gamma=0.0,
+             sigma_z_edge=0.0) -> Geometry:
+    """sigma_z_edge: relative rise of sigma_z from the strip centre to its ends (0: constant)."""
     return Geometry(float(R), float(L), float(sigma_z), float(sigma_dl), float(gamma), float(pixel), int(n_y),
-                    int(n_z), int(kernel_variant), 0)
+                    int(n_z), int(kernel_variant), 0, float(sigma_z_edge))
 
 
 def _stream(stream=None):
@@ -195,9 +198,15 @@ def prepare(g: Geometry, events: torch.Tensor, ws: torch.Tensor, stream=None):
                                     _stream(stream)), "jpet_mlem_prepare")
 
 
+_SPLIT = {None: 0, "wave": JPET_PASS_WAVE_PER_EVENT, "thread": JPET_PASS_THREAD_PER_EVENT}
+
+
 def mlem_iterate(g: Geometry, events: torch.Tensor, rho: torch.Tensor, n_iter: int, s: torch.Tensor | None = None,
-                 ws: torch.Tensor | None = None, prepared: bool = False, want_stats: bool = False, stream=None):
-    """n_iter MLEM iterations in place on rho; returns the stats dict when want_stats."""
+                 ws: torch.Tensor | None = None, prepared: bool = False, want_stats: bool = False, stream=None,
+                 split: str | None = None):
+    """n_iter MLEM iterations in place on rho; returns the stats dict when want_stats.
+    split: None (the planned pass) or, for comparison, "wave" (one wavefront per event) or
+    "thread" (one thread per event)."""
     _events(events)
     _need(rho, "rho", torch.float32, g.shape)
     if s is not None:
@@ -207,7 +216,7 @@ def mlem_iterate(g: Geometry, events: torch.Tensor, rho: torch.Tensor, n_iter: i
         prepared = False
     st = Stats() if want_stats else None
     rc = _lib().jpet_mlem_iterate(ctypes.byref(g), _ptr(events), events.shape[0], _ptr(s), _ptr(rho), int(n_iter),
-                                  _ptr(ws), ws.numel(), JPET_WS_PREPARED if prepared else 0,
+                                  _ptr(ws), ws.numel(), (JPET_WS_PREPARED if prepared else 0) | _SPLIT[split],
                                   ctypes.byref(st) if st is not None else None, _stream(stream))
     _check(rc, "jpet_mlem_iterate")
     return st.as_dict() if st is not None else None
@@ -230,8 +239,9 @@ def accumulator(g: Geometry, device=None) -> torch.Tensor:
 
 
 def backproject(g: Geometry, events: torch.Tensor, rho: torch.Tensor, acc: torch.Tensor, ws: torch.Tensor | None = None,
-                prepared: bool = False, want_stats: bool = False, stream=None):
-    """One event pass over this event list, added into acc (see jpet_mlem_backproject)."""
+                prepared: bool = False, want_stats: bool = False, stream=None, split: str | None = None):
+    """One event pass over this event list, added into acc (see jpet_mlem_backproject); split as
+    for mlem_iterate."""
     _events(events)
     _need(rho, "rho", torch.float32, g.shape)
     _need(acc, "acc", torch.int64, g.shape)
@@ -240,7 +250,7 @@ def backproject(g: Geometry, events: torch.Tensor, rho: torch.Tensor, acc: torch
         prepared = False
     st = Stats() if want_stats else None
     rc = _lib().jpet_mlem_backproject(ctypes.byref(g), _ptr(events), events.shape[0], _ptr(rho), _ptr(acc), _ptr(ws),
-                                      ws.numel(), JPET_WS_PREPARED if prepared else 0,
+                                      ws.numel(), (JPET_WS_PREPARED if prepared else 0) | _SPLIT[split],
                                       ctypes.byref(st) if st is not None else None, _stream(stream))
     _check(rc, "jpet_mlem_backproject")
     return st.as_dict() if st is not None else None
@@ -423,7 +433,7 @@ class JPetLogLik(torch.autograd.Function):
     def forward(ctx, rho, sigma_z, sigma_dl, events, g, s=None, sigma_mask=None):
         sz = float(sigma_z)
         sd = float(sigma_dl)
-        gg = Geometry(g.R, g.L, sz, sd, g.gamma, g.pixel, g.n_y, g.n_z, g.kernel_variant, 0)
+        gg = Geometry(g.R, g.L, sz, sd, g.gamma, g.pixel, g.n_y, g.n_z, g.kernel_variant, 0, g.sigma_z_edge)
         mask = (sz, sd) if sigma_mask is None else tuple(float(x) for x in sigma_mask)
         res = loglik_grad(gg, events, rho.detach().contiguous(), s=s, sigma_mask=mask,
                           want_grad_rho=ctx.needs_input_grad[0])

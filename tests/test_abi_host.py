@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_strerror(lib):
-    assert lib.jpet_abi_version() == 1
+    assert lib.jpet_abi_version() == 2
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.jpet_strerror(code)
     assert lib.jpet_strerror(-99) == b"unknown status"
@@ -66,10 +66,29 @@ GOOD = dict(R=450.0, L=500.0, sigma_z=10.0, sigma_dl=63.0, pixel=2.0, n_y=400, n
     (dict(gamma=-0.001), jpet.JPET_OK),
     (dict(gamma=0.002), jpet.JPET_EDOMAIN),
     (dict(gamma=float("nan")), jpet.JPET_EDOMAIN),
+    (dict(sigma_z_edge=0.1), jpet.JPET_OK),          # sigma_z 10% higher at the strip ends
+    (dict(sigma_z_edge=1.0), jpet.JPET_OK),
+    (dict(sigma_z_edge=-0.1), jpet.JPET_EDOMAIN),
+    (dict(sigma_z_edge=1.5), jpet.JPET_EDOMAIN),
+    (dict(sigma_z_edge=float("nan")), jpet.JPET_EDOMAIN),
+    (dict(gamma=0.00105), jpet.JPET_OK),             # C^-1 positive definite at sigma_z ...
+    (dict(gamma=0.00105, sigma_z_edge=0.1), jpet.JPET_EDOMAIN),  # ... but not at 1.1 sigma_z
 ])
 def test_geometry_validation(lib, over, code):
     g = jpet.geometry(**{**GOOD, **over})
     assert ws_size(g, 10)[0] == code
+
+
+def test_position_dependent_sigma_z(lib):
+    """A larger sigma_z at the strip ends widens the plan's ellipse bound; the log-likelihood is
+    not defined for it."""
+    g0 = jpet.geometry(**GOOD)
+    g1 = jpet.geometry(**GOOD, sigma_z_edge=0.4)
+    assert ws_size(g1, 10**6)[1] > ws_size(g0, 10**6)[1]
+    b = ctypes.c_size_t(0)
+    assert lib.jpet_loglik_workspace_size(ctypes.byref(g1), None, 10, ctypes.byref(b)) == jpet.JPET_ENOTSUP
+    assert lib.jpet_loglik_workspace_size(ctypes.byref(g0), None, 10, ctypes.byref(b)) == jpet.JPET_OK
+    assert ctypes.sizeof(jpet.Geometry) == 72
 
 
 def test_workspace_size_grows_with_events(lib):
@@ -94,6 +113,7 @@ def test_entry_points_reject_bad_arguments_before_any_device_work(lib):
     assert lib.jpet_mlem_iterate(gp, fake, 5, None, None, 1, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
     assert lib.jpet_mlem_iterate(gp, fake, 5, None, fake, -1, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
     assert lib.jpet_mlem_iterate(gp, fake, 5, None, fake, 1, aligned_ws, 1 << 40, 8, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_iterate(gp, fake, 5, None, fake, 1, aligned_ws, 1 << 40, 6, None, None) == jpet.JPET_EINVAL
     # workspace: NULL, misaligned, too small
     assert lib.jpet_mlem_iterate(gp, fake, 5, None, fake, 1, None, 1 << 40, 0, None, None) == jpet.JPET_EWORKSPACE
     assert lib.jpet_mlem_iterate(gp, fake, 5, None, fake, 1, ctypes.c_void_p(0x100004), 1 << 40, 0, None,
@@ -119,7 +139,9 @@ def test_entry_points_reject_bad_arguments_before_any_device_work(lib):
     # back-projection into a caller accumulator: NULL accumulator, NULL rho, unknown flags, workspace
     assert lib.jpet_mlem_backproject(gp, fake, 5, fake, None, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
     assert lib.jpet_mlem_backproject(gp, fake, 5, None, fake, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
-    assert lib.jpet_mlem_backproject(gp, fake, 5, fake, fake, aligned_ws, 1 << 40, 2, None, None) == jpet.JPET_EINVAL
+    for bad_flags in (8, 6):  # unknown flag; both comparison work splits at once
+        assert lib.jpet_mlem_backproject(gp, fake, 5, fake, fake, aligned_ws, 1 << 40, bad_flags, None,
+                                         None) == jpet.JPET_EINVAL
     assert lib.jpet_mlem_backproject(gp, fake, 5, fake, fake, aligned_ws, 16, 0, None, None) == jpet.JPET_EWORKSPACE
     assert lib.jpet_mlem_update(gp, None, None, fake, None) == jpet.JPET_EINVAL
     assert lib.jpet_mlem_update(gp, None, fake, None, None) == jpet.JPET_EINVAL

@@ -122,6 +122,24 @@ def test_paper_setting_matches_oracle():
     assert rel_l2(got, want) <= 1e-4
 
 
+@pytest.mark.parametrize("split", ["wave", "thread"])
+def test_comparison_work_splits_match_oracle(tiny, split):
+    """The event pass run one wavefront or one thread per event (the paper's GPU granularities,
+    kept for comparison) gives the oracle's iterates, on the small grid and the paper's setting."""
+    w, ev_np, ev = tiny
+    for wl, n in ((w, len(ev_np)), (get_workload("paper130"), 20_000)):
+        g, go = geoms(wl)
+        e_np = ev_np if wl is w else wl.events(n)
+        so = oracle.sensitivity(go)
+        rho0 = oracle.initial_image(so)
+        s = jpet.sensitivity(g)
+        rho = torch.from_numpy(rho0.astype(np.float32)).to(DEV)
+        st = jpet.mlem_iterate(g, torch.from_numpy(e_np).to(DEV), rho, 2, s=s, want_stats=True, split=split)
+        want, sto = oracle.mlem(go, e_np, rho0, 2, s=so)
+        assert st["n_pairs"] == sto["n_pairs"] and st["n_valid"] == sto["n_valid"]
+        assert rel_l2(rho.cpu().numpy(), want) <= 1e-4, wl.name
+
+
 def test_count_conservation_gpu(tiny):
     w, _, ev = tiny
     g, _ = geoms(w)
@@ -213,17 +231,70 @@ def test_long_rows_and_many_rows():
     assert rel_l2(got, want) <= 1e-4
 
 
-def test_rows_longer_than_the_register_cache_use_the_generic_pass():
+@pytest.mark.parametrize("edge", [0.0, 0.3])
+def test_rows_longer_than_the_register_cache_use_the_generic_pass(edge):
     """Rows of more than 64 pixels (sigma_z = 12 mm on 0.5 mm pixels): the one-wavefront-per-event
-    pass with global accumulation."""
+    pass with global accumulation (also with sigma_z rising towards the strip ends)."""
     from jpet_synth import Workload
     w = Workload("fine", 450.0, 500.0, 12.0, 40.0, 0.5, 256, 256, 1500, 1, 11, "c1")
-    g, go = geoms(w)
+    g, go = geoms(w, sigma_z_edge=edge)
     assert jpet.launch_info(g, w.n_events)["binned"] == 0
     ev_np = w.events()
     got, want, st, sto = run_both(g, go, ev_np, np.ones((256, 256)))
     assert st["n_pairs"] == sto["n_pairs"]
     assert rel_l2(got, want) <= 1e-4
+
+
+# ---------------------------------------------------------------------------------------------
+# sigma_z depending on the hit positions (Sec. 3 after Eq. 12): one sigma_z per event
+
+
+@pytest.mark.parametrize("edge", [0.1, 1.0])
+def test_position_dependent_sigma_z_tiny(tiny, edge):
+    """Two iterations from rho^0 on the small grid; events near the strip ends get ellipses up to
+    (1 + edge) times wider."""
+    w, ev_np, ev = tiny
+    g, go = geoms(w, sigma_z_edge=edge)
+    so = oracle.sensitivity(go)
+    got, want, st, sto = run_both(g, go, ev_np, oracle.initial_image(so), n_iter=2)
+    assert st["n_pairs"] == sto["n_pairs"] and st["n_valid"] == sto["n_valid"]
+    assert rel_l2(got, want) <= 1e-4
+    g0, go0 = geoms(w)
+    assert st["n_pairs"] > oracle.mlem(go0, ev_np, oracle.initial_image(so), 1, s=so)[1]["n_pairs"]
+    # the log-likelihood is defined for one sigma_z shared by all events
+    with pytest.raises(jpet.JpetError):
+        jpet.loglik_grad(g, ev, torch.from_numpy(want.astype(np.float32)).to(DEV), s=jpet.sensitivity(g))
+
+
+def test_position_dependent_sigma_z_edge400_first_events():
+    """The edge400 workload (400x400 px of 2 mm, sigma_z 10 mm rising 10% to the strip ends):
+    the first 30k events, two iterations from rho^0."""
+    w = get_workload("edge400")
+    g, go = geoms(w)
+    ev_np = w.events(30_000)
+    so = oracle.sensitivity(go)
+    got, want, st, sto = run_both(g, go, ev_np, oracle.initial_image(so), n_iter=2)
+    assert st["n_pairs"] == sto["n_pairs"] and st["n_valid"] == sto["n_valid"]
+    assert rel_l2(got, want) <= 1e-4
+
+
+def test_position_dependent_sigma_z_in_a_batch(tiny):
+    """An instance with a position-dependent sigma_z inside a batch equals its single call."""
+    w, ev_np, ev = tiny
+    inst, imgs, singles = [], [], []
+    for edge in (0.0, 0.25):
+        g = jpet.geometry(**w.geometry(sigma_z_edge=edge))
+        s = jpet.sensitivity(g)
+        rho = (s > 0).to(torch.float32)
+        inst.append((g, ev, s, rho))
+        imgs.append(rho)
+        r1 = (s > 0).to(torch.float32)
+        jpet.mlem_iterate(g, ev, r1, 2, s=s)
+        singles.append(r1)
+    jpet.BatchedMLEM(inst).iterate(2)
+    for a, b in zip(imgs, singles):
+        assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-6
+    assert rel_l2(imgs[0].cpu().numpy(), imgs[1].cpu().numpy()) > 1e-3
 
 
 # ---------------------------------------------------------------------------------------------
@@ -279,6 +350,34 @@ def test_prod400_sampled_parity(prod):
         acc = np.sum(pool.map(_oracle_backprojection_chunk, jobs), axis=0)
     got = rho.double().cpu().numpy().ravel()[pix] * so.ravel()[pix]
     print(f"prod400: sampled pixels GPU {got} oracle {acc}", flush=True)
+    np.testing.assert_allclose(got, acc, rtol=1e-5)
+
+
+def test_edge400_full_size_sampled_parity():
+    """All 10M events of edge400, one iteration: count conservation over the image and the new
+    image at sampled pixels against the oracle (every event whose box reaches them)."""
+    import multiprocessing as mp
+    w = get_workload("edge400")
+    ev_np = w.events()
+    ev = torch.from_numpy(ev_np).to(DEV)
+    g, go = geoms(w)
+    s = jpet.sensitivity(g)
+    so = oracle.sensitivity(go)
+    rho = (s > 0).to(torch.float32)
+    st = jpet.mlem_iterate(g, ev, rho, 1, s=s, want_stats=True)
+    assert st["n_unplaced_rows"] == 0
+    print(f"edge400: GPU iteration done, {st}", flush=True)
+    total = float((s.double() * rho.double()).sum())
+    assert total == pytest.approx(st["n_valid"] - st["n_zero_denominator"], rel=1e-6)
+    # the centre and pixels near the phantom's edges
+    pix = [200 * 400 + 200, 230 * 400 + 140, 170 * 400 + 260, 260 * 400 + 250, 140 * 400 + 150]
+    nproc = 16
+    r0 = oracle.initial_image(so).ravel()
+    jobs = [(w.geometry(), c, r0, pix) for c in np.array_split(ev_np, nproc)]
+    with mp.get_context("spawn").Pool(nproc) as pool:
+        acc = np.sum(pool.map(_oracle_backprojection_chunk, jobs), axis=0)
+    got = rho.double().cpu().numpy().ravel()[pix] * so.ravel()[pix]
+    print(f"edge400: sampled pixels GPU {got} oracle {acc}", flush=True)
     np.testing.assert_allclose(got, acc, rtol=1e-5)
 
 
