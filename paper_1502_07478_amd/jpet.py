@@ -373,6 +373,11 @@ class BatchedMLEM:
                                                 JPET_WS_PREPARED, st, _stream(stream)), "jpet_mlem_batched_iterate")
         return [st[k].as_dict() for k in range(self.count)] if want_stats else None
 
+    def run(self, n_iter: int = 10, want_stats: bool = False, stream=None):
+        """The whole reconstruction of every instance: n_iter iterations (the batched workload
+        runs 10); the images are updated in place."""
+        return self.iterate(n_iter, want_stats=want_stats, stream=stream)
+
 
 @dataclass
 class LogLik:

@@ -88,7 +88,7 @@ def test_batched_equals_single_instance_calls():
     base = batch_instances()[:6]
     ws_list = [(w, w.events(4000)) for w in base]
     inst, images = _setup(ws_list, True)
-    jpet.BatchedMLEM(inst).iterate(3)
+    jpet.BatchedMLEM(inst).run(3)
     for (w, ev_np), got in zip(ws_list, images):
         g = jpet.geometry(**w.geometry())
         s = jpet.sensitivity(g)
