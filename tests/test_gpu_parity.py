@@ -194,6 +194,36 @@ def test_single_event_and_ragged_grid(tiny):
             assert rel_l2(got, want) <= 1e-4
 
 
+def test_hot_spot_of_identical_events(tiny):
+    """60k copies of three events among 5k ordinary ones: one bin holds most of the list (many
+    workgroup items on the same region, all adding to the same pixels)."""
+    w, ev_np, _ = tiny
+    g, go = geoms(w)
+    hot = np.repeat(ev_np[:3], 20_000, axis=0)
+    ev = np.concatenate([hot, ev_np[3:5003]])
+    rng = np.random.default_rng(3)
+    ev = np.ascontiguousarray(ev[rng.permutation(len(ev))])
+    so = oracle.sensitivity(go)
+    got, want, st, sto = run_both(g, go, ev, oracle.initial_image(so), n_iter=2)
+    assert st["n_pairs"] == sto["n_pairs"] and st["n_valid"] == sto["n_valid"]
+    assert rel_l2(got, want) <= 1e-4
+
+
+def test_large_grid_with_many_bins():
+    """A 2048x2048 grid of 0.2 mm (4M pixels, thousands of bins) with sigma = (1.5, 9) mm: 20k
+    events, two iterations from rho^0."""
+    from jpet_synth import Workload
+    w = Workload("grid2048", 450.0, 500.0, 1.5, 9.0, 0.2, 2048, 2048, 20_000, 2, 13, "c1")
+    g, go = geoms(w)
+    info = jpet.launch_info(g, w.n_events)
+    assert info["binned"] == 1 and info["bins"] > 1000
+    ev_np = w.events()
+    so = oracle.sensitivity(go)
+    got, want, st, sto = run_both(g, go, ev_np, oracle.initial_image(so), n_iter=2)
+    assert st["n_pairs"] == sto["n_pairs"] and st["n_valid"] == sto["n_valid"]
+    assert rel_l2(got, want) <= 1e-4
+
+
 def test_zero_denominator_events_are_skipped(tiny):
     w, ev_np, _ = tiny
     g, go = geoms(w)
