@@ -1,4 +1,4 @@
-"""Build libjpet.so (gfx950) in-tree with hipcc."""
+"""Build libjpet.so (gfx950) and the rate microbenchmark in-tree with hipcc."""
 
 from __future__ import annotations
 
@@ -9,6 +9,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libjpet.so")
+MICROBENCH = os.path.join(HERE, "microbench")
 ARCH = os.environ.get("JPET_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled: the compiler would otherwise pair ordinary float
@@ -37,7 +38,21 @@ def build(verbose: bool = False) -> str:
         if out.strip():
             print(out)
     os.replace(tmp, LIB)
+    build_microbench(hipcc)
     return LIB
+
+
+def build_microbench(hipcc: str | None = None) -> str:
+    """The instruction-rate probes (microbench.hip) as a stand-alone executable."""
+    hipcc = hipcc or os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = MICROBENCH + f".tmp{os.getpid()}"
+    flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
+    res = subprocess.run([hipcc, *flags, "-o", tmp, os.path.join(HERE, "microbench.hip")], capture_output=True,
+                         text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed (microbench):\n" + res.stdout + res.stderr)
+    os.replace(tmp, MICROBENCH)
+    return MICROBENCH
 
 
 if __name__ == "__main__":
