@@ -140,13 +140,16 @@ int jpet_direct_image(const jpet_geometry* g, const float* events, int64_t n, fl
 
 /* Bytes of workspace that jpet_mlem_prepare / jpet_mlem_iterate / jpet_mlem_backproject need for
  * n_events events on this geometry (host output *bytes).  The workspace is any device
- * allocation of at least that size, aligned to 256 bytes. */
+ * allocation of at least that size, aligned to 256 bytes.
+ * Every entry point takes at most 2^31 - 1 events per call (else JPET_EINVAL): event positions
+ * and bin offsets are 32-bit on the device.  Longer lists are processed in pieces with
+ * jpet_mlem_backproject and jpet_mlem_update. */
 int jpet_mlem_workspace_size(const jpet_geometry* g, int64_t n_events, size_t* bytes);
 
 /* Iteration-invariant per-event work, done once per event list: direct reconstruction (Eq. 2),
  * the 3-sigma ellipse's pixel rows (App. B) and validity, and the spatial ordering of events
  * used by the event pass.  Writes only the workspace.
- *   events: device float [n][3]; n >= 0. */
+ *   events: device float [n][3]; 0 <= n <= 2^31 - 1. */
 int jpet_mlem_prepare(const jpet_geometry* g, const float* events, int64_t n, void* ws, size_t ws_bytes,
                       void* stream);
 

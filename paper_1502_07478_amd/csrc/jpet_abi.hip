@@ -39,6 +39,10 @@ int hip_fail(hipError_t e) {
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
+// Events per call: event positions and bin offsets are 32-bit on the device.  Longer lists go
+// through jpet_mlem_backproject in pieces.
+constexpr int64_t kMaxEvents = 2147483647;
+
 // Full validation of the geometry (before anything is enqueued).
 int check_geometry(const jpet_geometry* g) {
   if (!g) return JPET_EINVAL;
@@ -393,7 +397,8 @@ int check_instances(const jpet_instance* inst, int32_t count) {
   for (int k = 0; k < count; ++k) {
     const int rc = check_geometry(&inst[k].g);
     if (rc) return rc;
-    if (inst[k].n < 0 || (inst[k].n > 0 && !inst[k].events) || !inst[k].rho) return JPET_EINVAL;
+    if (inst[k].n < 0 || inst[k].n > kMaxEvents || (inst[k].n > 0 && !inst[k].events) || !inst[k].rho)
+      return JPET_EINVAL;
   }
   return JPET_OK;
 }
@@ -500,7 +505,7 @@ int jpet_sensitivity(const jpet_geometry* g, float* s_out, void* stream) {
 int jpet_mlem_workspace_size(const jpet_geometry* g, int64_t n_events, size_t* bytes) {
   int rc = check_geometry(g);
   if (rc) return rc;
-  if (!bytes || n_events < 0) return JPET_EINVAL;
+  if (!bytes || n_events < 0 || n_events > kMaxEvents) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n_events);
   *bytes = workspace_layout(p, n_events, npix_of(g), nullptr, nullptr);
   return JPET_OK;
@@ -519,7 +524,7 @@ int jpet_direct_image(const jpet_geometry* g, const float* events, int64_t n, fl
 int jpet_loglik_workspace_size(const jpet_geometry* g, const double* sigma_mask, int64_t n_events, size_t* bytes) {
   int rc = check_geometry(g);
   if (rc) return rc;
-  if (!bytes || n_events < 0) return JPET_EINVAL;
+  if (!bytes || n_events < 0 || n_events > kMaxEvents) return JPET_EINVAL;
   if (g->sigma_z_edge != 0.0) return JPET_ENOTSUP;  // defined for one sigma_z for all events
   double msz = g->sigma_z, mdl = g->sigma_dl;
   if (sigma_mask) {
@@ -535,7 +540,7 @@ int jpet_loglik_workspace_size(const jpet_geometry* g, const double* sigma_mask,
 int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_info* info) {
   int rc = check_geometry(g);
   if (rc) return rc;
-  if (!info || n_events < 0) return JPET_EINVAL;
+  if (!info || n_events < 0 || n_events > kMaxEvents) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n_events);
   memset(info, 0, sizeof(*info));
   info->binned = p.tiled;
@@ -560,7 +565,7 @@ int jpet_mlem_prepare(const jpet_geometry* g, const float* events, int64_t n, vo
                       void* stream) {
   int rc = check_geometry(g);
   if (rc) return rc;
-  if (n < 0 || (n > 0 && !events)) return JPET_EINVAL;
+  if (n < 0 || n > kMaxEvents || (n > 0 && !events)) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
   Workspace w;
   rc = carve(p, g, n, ws, ws_bytes, &w);
@@ -573,7 +578,7 @@ int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, co
                       void* stream) {
   int rc = check_geometry(g);
   if (rc) return rc;
-  if (n < 0 || (n > 0 && !events) || !rho || n_iter < 0) return JPET_EINVAL;
+  if (n < 0 || n > kMaxEvents || (n > 0 && !events) || !rho || n_iter < 0) return JPET_EINVAL;
   const int gran = pass_granularity(flags);
   if (gran < 0) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
@@ -602,7 +607,7 @@ int jpet_mlem_backproject(const jpet_geometry* g, const float* events, int64_t n
                           void* ws, size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream) {
   int rc = check_geometry(g);
   if (rc) return rc;
-  if (n < 0 || (n > 0 && !events) || !rho || !acc) return JPET_EINVAL;
+  if (n < 0 || n > kMaxEvents || (n > 0 && !events) || !rho || !acc) return JPET_EINVAL;
   const int gran = pass_granularity(flags);
   if (gran < 0) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
@@ -639,7 +644,7 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
                      size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream) {
   int rc = check_geometry(g);
   if (rc) return rc;
-  if (n < 0 || (n > 0 && !events) || !rho || !out3) return JPET_EINVAL;
+  if (n < 0 || n > kMaxEvents || (n > 0 && !events) || !rho || !out3) return JPET_EINVAL;
   if (flags & ~JPET_WS_PREPARED) return JPET_EINVAL;
   if (g->sigma_z_edge != 0.0) return JPET_ENOTSUP;  // defined for one sigma_z for all events
   double msz = g->sigma_z, mdl = g->sigma_dl;

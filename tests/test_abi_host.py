@@ -97,6 +97,8 @@ def test_workspace_size_grows_with_events(lib):
     rc1, b1 = ws_size(g, 1000)
     assert rc0 == 0 and rc1 == 0 and b1 > b0 > 0
     assert ws_size(g, -1)[0] == jpet.JPET_EINVAL
+    assert ws_size(g, 2**31 - 1)[0] == jpet.JPET_OK
+    assert ws_size(g, 2**31)[0] == jpet.JPET_EINVAL  # 32-bit event positions on the device
     assert ws_size(None, 10)[0] == jpet.JPET_EINVAL
 
 
