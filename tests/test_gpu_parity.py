@@ -224,6 +224,74 @@ def test_large_grid_with_many_bins():
     assert rel_l2(got, want) <= 1e-4
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_random_geometries(seed):
+    """Random detector, resolution, grid (some binned, some generic), kernel variant, gamma and
+    position-dependent sigma_z; valid events plus non-finite, off-strip, strip-end and off-grid ones.
+    Counts exact, images finite and within 1e-4 of the oracle over two iterations."""
+    from jpet_synth import Workload
+    rng = np.random.default_rng(4100 + seed)
+    R = float(rng.uniform(120, 500))
+    L = float(rng.uniform(200, 1000))
+    sz, sdl = float(rng.uniform(3, 15)), float(rng.uniform(20, 90))
+    n_y, n_z = int(rng.integers(16, 160)), int(rng.integers(16, 200))
+    pixel = float(rng.uniform(0.05, 0.95)) * 2.0 * R / n_y
+    pixel = max(pixel, sz / 30.0) if 0.5 * n_y * max(pixel, sz / 30.0) < R else pixel
+    edge = float(rng.choice([0.0, 0.2]))
+    szm = sz * (1 + edge)
+    gamma = float(rng.choice([0.0, 0.5, -0.6])) * math.sqrt(1 / szm ** 2 / sdl ** 2 / 2)
+    variant = int(rng.integers(0, 2))
+    pairs_est = math.pi * (1.5 * sdl / pixel) * (2.2 * szm / pixel)
+    n = int(max(50, min(2000, 2e7 / max(pairs_est, 1.0))))
+    w = Workload(f"fuzz{seed}", R, L, sz, sdl, pixel, n_y, n_z, n, 2, 5000 + seed, "random", sigma_z_edge=edge)
+    ev = w.events()
+    odd = np.array([[np.nan, 0, 0], [0, np.inf, 0], [0.5 * L + 1, 0, 0], [0, -0.5 * L - 1, 0],
+                    [0.5 * L, -0.5 * L, 0], [0.5 * L, 0.5 * L, 10.0], [0, 0, 50 * R], [-0.5 * L, 0.25 * L, -30.0]],
+                   np.float32)
+    ev = np.ascontiguousarray(np.concatenate([ev, odd]))
+    g, go = geoms(w, kernel_variant=variant, gamma=gamma)
+    so = oracle.sensitivity(go)
+    got, want, st, sto = run_both(g, go, ev, oracle.initial_image(so), n_iter=2)
+    assert np.all(np.isfinite(got))
+    for k in ("n_valid", "n_dropped", "n_pairs", "n_zero_denominator"):
+        assert st[k] == sto[k], (k, st[k], sto[k])
+    if np.linalg.norm(want) > 0:
+        assert rel_l2(got, want) <= 1e-4
+
+
+def test_repeated_runs_agree(tiny):
+    """Back-projection sums are integers, so only the order of the double-precision denominator
+    sums can differ between runs."""
+    w, ev_np, ev = tiny
+    g, _ = geoms(w)
+    s = jpet.sensitivity(g)
+    imgs = []
+    for _ in range(3):
+        rho = (s > 0).to(torch.float32)
+        jpet.mlem_iterate(g, ev, rho, 5, s=s)
+        imgs.append(rho.cpu().numpy())
+    for a in imgs[1:]:
+        assert rel_l2(a, imgs[0]) <= 1e-6
+
+
+def test_resume_from_a_saved_image(tiny):
+    """MLEM keeps no state besides the image: 2 iterations, a round trip of the image through host
+    memory, then 3 more equal 5 iterations at once."""
+    w, ev_np, ev = tiny
+    g, _ = geoms(w)
+    s = jpet.sensitivity(g)
+    ws = jpet.workspace(g, ev.shape[0])
+    jpet.prepare(g, ev, ws)
+    a = (s > 0).to(torch.float32)
+    jpet.mlem_iterate(g, ev, a, 5, s=s, ws=ws, prepared=True)
+    b = (s > 0).to(torch.float32)
+    jpet.mlem_iterate(g, ev, b, 2, s=s, ws=ws, prepared=True)
+    saved = b.cpu().numpy().copy()
+    c = torch.from_numpy(saved).to(DEV)
+    jpet.mlem_iterate(g, ev, c, 3, s=s, ws=ws, prepared=True)
+    assert rel_l2(c.cpu().numpy(), a.cpu().numpy()) <= 1e-6
+
+
 def test_zero_denominator_events_are_skipped(tiny):
     w, ev_np, _ = tiny
     g, go = geoms(w)
