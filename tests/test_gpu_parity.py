@@ -502,6 +502,40 @@ def test_loglik_and_gradients_match_oracle(tiny, variant):
     assert res.stats["n_pairs"] == sto["n_pairs"]
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_loglik_random_geometries(seed):
+    """The log-likelihood and its gradients on random geometries (binned and generic passes, both
+    kernel variants, gamma, a mask at other sigmas) against the oracle, at a textured image."""
+    from jpet_synth import Workload
+    rng = np.random.default_rng(4200 + seed)
+    R = float(rng.uniform(150, 500))
+    L = float(rng.uniform(250, 900))
+    sz, sdl = float(rng.uniform(4, 14)), float(rng.uniform(25, 85))
+    n_y, n_z = int(rng.integers(24, 120)), int(rng.integers(24, 160))
+    pixel = min(float(rng.uniform(0.5, 6.0)), 1.9 * R / n_y)
+    gamma = float(rng.choice([0.0, 0.4, -0.5])) * math.sqrt(1 / sz ** 2 / sdl ** 2 / 2)
+    variant = int(rng.integers(0, 2))
+    pairs_est = math.pi * (1.5 * sdl / pixel) * (2.2 * sz / pixel)
+    n = int(max(50, min(1500, 1e7 / max(pairs_est, 1.0))))
+    w = Workload(f"llfuzz{seed}", R, L, sz, sdl, pixel, n_y, n_z, n, 1, 6000 + seed, "random")
+    ev_np = w.events()
+    mask = (sz * float(rng.uniform(0.9, 1.1)), sdl * float(rng.uniform(0.9, 1.1))) if seed % 2 else None
+    g, go = geoms(w, kernel_variant=variant, gamma=gamma)
+    so = oracle.sensitivity(go)
+    r_np = ((so > 0) * (0.5 + np.random.default_rng(seed).random(so.shape))).astype(np.float32)
+    rho = torch.from_numpy(r_np).to(DEV)
+    res = jpet.loglik_grad(g, torch.from_numpy(ev_np).to(DEV), rho, s=jpet.sensitivity(g), sigma_mask=mask,
+                           want_stats=True)
+    l, dz, dd, gr, sto = oracle.loglik_grad(go, ev_np, r_np.astype(np.float64), s=so, sigma_mask=mask)
+    assert res.stats["n_pairs"] == sto["n_pairs"] and res.stats["n_valid"] == sto["n_valid"]
+    v = res.value.cpu().numpy()
+    if sto["n_zero_denominator"] == 0 and sto["n_valid"] > 0:
+        assert v[0] == pytest.approx(l, rel=1e-6)
+        assert v[1] == pytest.approx(dz, rel=1e-3, abs=1e-6 * abs(l))
+        assert v[2] == pytest.approx(dd, rel=1e-3, abs=1e-6 * abs(l))
+        assert rel_l2(res.grad_rho.cpu().numpy(), gr) <= 1e-4
+
+
 def test_loglik_sigma_gradient_matches_gpu_finite_differences(tiny):
     w, ev_np, ev = tiny
     g, go = geoms(w)
