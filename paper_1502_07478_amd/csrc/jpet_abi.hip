@@ -22,6 +22,30 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
 
+// Side streams on which the kernel groups of a batched event pass run side by side, so that one
+// group's last workgroups overlap the next group's first ones.  Created once per device, at the
+// default priority, and kept until the process ends; calls fork them from and join them to their
+// own stream with events, so calls on different streams stay ordered.
+constexpr int kSideStreams = 3;
+std::mutex g_side_mu;
+std::vector<std::vector<hipStream_t>> g_side;
+
+hipError_t side_streams(hipStream_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  if ((int)g_side.size() <= dev) g_side.resize(dev + 1);
+  std::vector<hipStream_t>& v = g_side[dev];
+  while ((int)v.size() < kSideStreams) {
+    hipStream_t s = nullptr;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return e;
+    v.push_back(s);
+  }
+  *out = v.data();
+  return hipSuccess;
+}
+
 void prof_forget_locked() {
   for (auto& pr : g_prof_events) {
     (void)hipEventDestroy(pr.first);
@@ -758,14 +782,43 @@ int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t 
   }
   for (int k = 0; k < count; ++k)
     if ((e = launch_fill_u64(w[k].acc, npix_of(&inst[k].g), st)) != hipSuccess) return hip_fail(e);
+  // groups after the first run on side streams (forked from and joined to st every iteration)
+  const int nside = std::min<int>(kSideStreams, (int)L.group.size() - 1);
+  hipStream_t* side = nullptr;
+  hipEvent_t fork = nullptr, join[kSideStreams] = {};
+  if (nside > 0) {
+    if ((e = side_streams(&side)) != hipSuccess) return hip_fail(e);
+    if ((e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
+    for (int i = 0; i < nside; ++i)
+      if ((e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
+  }
+  struct EventGuard {  // recorded events may still be pending: the runtime releases them when done
+    hipEvent_t* f;
+    hipEvent_t* j;
+    int n;
+    ~EventGuard() {
+      if (*f) (void)hipEventDestroy(*f);
+      for (int i = 0; i < n; ++i)
+        if (j[i]) (void)hipEventDestroy(j[i]);
+    }
+  } guard{&fork, join, nside};
   for (int it = 0; it < n_iter; ++it) {
     if ((e = launch_batched_reset(table, count, st)) != hipSuccess) return hip_fail(e);
     rc = timed(
         [&] {
           hipError_t r = hipSuccess;
+          if (nside > 0) {
+            r = hipEventRecord(fork, st);
+            for (int i = 0; i < nside && r == hipSuccess; ++i) r = hipStreamWaitEvent(side[i], fork, 0);
+          }
           for (size_t gi = 0; gi < L.group.size() && r == hipSuccess; ++gi) {
             const BatchGroup& G = L.group[gi];
-            r = launch_event_pass_batched(table + G.first, G.count, G.maxlen, G.waves, G.acc32, G.lds, G.grid, st);
+            hipStream_t sg = gi == 0 ? st : side[(gi - 1) % nside];
+            r = launch_event_pass_batched(table + G.first, G.count, G.maxlen, G.waves, G.acc32, G.lds, G.grid, sg);
+          }
+          for (int i = 0; i < nside && r == hipSuccess; ++i) {
+            r = hipEventRecord(join[i], side[i]);
+            if (r == hipSuccess) r = hipStreamWaitEvent(st, join[i], 0);
           }
           return r;
         },
