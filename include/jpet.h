@@ -236,7 +236,10 @@ int jpet_mlem_batched_prepare(const jpet_instance* inst, int32_t count, void* ws
 /* n_iter MLEM iterations of every instance, in place on each rho.  flags: 0 or JPET_WS_PREPARED
  * (the workspace holds jpet_mlem_batched_prepare's output for the same instance array: same
  * geometries, event pointers and counts).  stats: host array of count entries, or NULL; entry k
- * describes instance k (the call then synchronises).  Instances must not share rho arrays. */
+ * describes instance k (the call then synchronises).  Instances must not share rho arrays.
+ * The work is ordered on stream as usual; inside each iteration, groups of instances that use
+ * different kernels run on up to three side streams that the library creates once per device
+ * (default priority) and forks from and joins back to stream with events. */
 int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t n_iter, void* ws, size_t ws_bytes,
                               uint32_t flags, jpet_stats* stats, void* stream);
 
