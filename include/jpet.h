@@ -6,8 +6,9 @@
  * two-strip J-PET tomograph" (arXiv:1502.07478):
  *   - events are the triples (z_u, z_d, dl) of the Setup section (Eq. 1),
  *   - the per-pixel sensitivity is Eq. 4,
- *   - the event kernel P(e|i) is Eq. 7 with the vectors of Eq. 8-11 and the diagonal
- *     C^-1 of Eq. 12 (including its off-diagonal gamma),
+ *   - the event kernel P(e|i) is Eq. 7 with the vectors of Eq. 8-11 and the C^-1 of
+ *     Eq. 12: diagonal as the paper assumes, or with its off-diagonal gamma, and with
+ *     sigma_z optionally depending on the event's hit positions,
  *   - it is evaluated over the pixel centres inside the 3-sigma ellipse of each event
  *     (Sec. 3, last paragraph; bounding box of App. B),
  *   - one iteration is the two-pass scheme of the implementation listing (Sec. 4):
