@@ -274,7 +274,9 @@ class ChunkedMLEM:
     events (exactly: the accumulator is an integer sum).
 
     resident=True keeps every chunk's events and prepared workspace in device memory, prepared
-    once (the fast path when they fit: at 288 GB per GPU they usually do).  resident=False keeps
+    once (the fast path when they fit: at 288 GB per GPU they usually do); odd chunks then run on a
+    side stream, so one chunk's last workgroups overlap the next chunk's first ones (the
+    accumulator's integer atomics make the order irrelevant).  resident=False keeps
     one device slot pair and streams the chunks through it every iteration, each copied on a side
     stream while the previous chunk is processed and prepared again on arrival.
     """
@@ -295,6 +297,7 @@ class ChunkedMLEM:
             self.ws = [workspace(g, c.shape[0], self.device) for c in self.ev]
             for e, w in zip(self.ev, self.ws):
                 prepare(g, e, w)
+            self.side = torch.cuda.Stream(device=self.device) if len(self.chunks) > 1 else None
         else:
             cap = max((c.shape[0] for c in self.chunks), default=0)
             self.slots = [torch.empty((cap, 3), dtype=torch.float32, device=self.device) for _ in range(2)]
@@ -306,15 +309,22 @@ class ChunkedMLEM:
     def iterate(self, rho: torch.Tensor, n_iter: int, want_stats: bool = False):
         """n_iter iterations in place on rho; the summed stats of the last iteration if asked."""
         tot = None
+        side = self.side if self.resident else None
+        cur = torch.cuda.current_stream(self.device)
         for it in range(n_iter):
             last = want_stats and it == n_iter - 1
             tot = {} if last else None
+            if side is not None:
+                side.wait_stream(cur)  # the image and the cleared accumulator are ready
             for k in range(len(self.chunks)):
                 ev, ws, prepared = self._chunk(k)
-                st = backproject(self.g, ev, rho, self.acc, ws=ws, prepared=prepared, want_stats=last)
+                st = backproject(self.g, ev, rho, self.acc, ws=ws, prepared=prepared, want_stats=last,
+                                 stream=side if side is not None and k % 2 == 1 else None)
                 if last:
                     for key, v in st.items():
                         tot[key] = tot.get(key, 0) + v
+            if side is not None:
+                cur.wait_stream(side)
             update(self.g, self.acc, rho, self.s)
         return tot
 
