@@ -276,9 +276,10 @@ class ChunkedMLEM:
     resident=True keeps every chunk's events and prepared workspace in device memory, prepared
     once (the fast path when they fit: at 288 GB per GPU they usually do); odd chunks then run on a
     side stream, so one chunk's last workgroups overlap the next chunk's first ones (the
-    accumulator's integer atomics make the order irrelevant).  resident=False keeps
-    one device slot pair and streams the chunks through it every iteration, each copied on a side
-    stream while the previous chunk is processed and prepared again on arrival.
+    accumulator's integer atomics make the order irrelevant).  resident=False keeps two device
+    slots (events and workspace) and streams the chunks through them every iteration: on a side
+    stream, the next chunk is copied from (pinned) host memory and prepared while the current one
+    is processed.
     """
 
     def __init__(self, g: Geometry, chunks, s: torch.Tensor | None = None, resident: bool = True, device=None):
@@ -301,10 +302,11 @@ class ChunkedMLEM:
         else:
             cap = max((c.shape[0] for c in self.chunks), default=0)
             self.slots = [torch.empty((cap, 3), dtype=torch.float32, device=self.device) for _ in range(2)]
-            # one workspace, prepared again for each chunk: the largest any chunk needs
+            # one workspace per slot, prepared again for each chunk: the largest any chunk needs
             wsb = max((workspace_size(g, c.shape[0]) for c in self.chunks), default=workspace_size(g, 0))
-            self.ws = [torch.empty(wsb, dtype=torch.uint8, device=self.device)]
+            self.ws = [torch.empty(wsb, dtype=torch.uint8, device=self.device) for _ in range(2)]
             self.copy_stream = torch.cuda.Stream(device=self.device)
+            self.ready = [torch.cuda.Event() for _ in range(2)]
 
     def iterate(self, rho: torch.Tensor, n_iter: int, want_stats: bool = False):
         """n_iter iterations in place on rho; the summed stats of the last iteration if asked."""
@@ -316,9 +318,12 @@ class ChunkedMLEM:
             tot = {} if last else None
             if side is not None:
                 side.wait_stream(cur)  # the image and the cleared accumulator are ready
+            if not self.resident and self.chunks:
+                self.copy_stream.wait_stream(cur)  # slot 0 is free once earlier work is done
+                self._stage(0)
             for k in range(len(self.chunks)):
-                ev, ws, prepared = self._chunk(k)
-                st = backproject(self.g, ev, rho, self.acc, ws=ws, prepared=prepared, want_stats=last,
+                ev, ws = self._chunk(k, cur)
+                st = backproject(self.g, ev, rho, self.acc, ws=ws, prepared=True, want_stats=last,
                                  stream=side if side is not None and k % 2 == 1 else None)
                 if last:
                     for key, v in st.items():
@@ -328,23 +333,26 @@ class ChunkedMLEM:
             update(self.g, self.acc, rho, self.s)
         return tot
 
-    def _chunk(self, k):
-        if self.resident:
-            return self.ev[k], self.ws[k], True
-        cur = torch.cuda.current_stream(self.device)
+    def _stage(self, k):
+        """On the copy stream: chunk k into slot k % 2, then its preparation into that slot's
+        workspace; the slot's event marks both done."""
         n = self.chunks[k].shape[0]
         slot = self.slots[k % 2]
-        if k == 0:  # first chunk of the iteration: copy now
-            slot[:n].copy_(self.chunks[0], non_blocking=True)
-        else:
-            cur.wait_stream(self.copy_stream)
-        if k + 1 < len(self.chunks):  # start the next copy once the slot it overwrites is free
-            nxt = self.slots[(k + 1) % 2]
-            m = self.chunks[k + 1].shape[0]
+        with torch.cuda.stream(self.copy_stream):
+            slot[:n].copy_(self.chunks[k], non_blocking=True)
+            prepare(self.g, slot[:n], self.ws[k % 2], stream=self.copy_stream)
+            self.ready[k % 2].record(self.copy_stream)
+
+    def _chunk(self, k, cur):
+        """Events and prepared workspace of chunk k for a pass enqueued next on cur."""
+        if self.resident:
+            return self.ev[k], self.ws[k]
+        if k + 1 < len(self.chunks):
+            # slot (k + 1) % 2 held chunk k - 1, whose pass is the last work enqueued on cur
             self.copy_stream.wait_stream(cur)
-            with torch.cuda.stream(self.copy_stream):
-                nxt[:m].copy_(self.chunks[k + 1], non_blocking=True)
-        return slot[:n], self.ws[0], False
+            self._stage(k + 1)
+        cur.wait_event(self.ready[k % 2])
+        return self.slots[k % 2][:self.chunks[k].shape[0]], self.ws[k % 2]
 
 
 class BatchedMLEM:
