@@ -258,8 +258,9 @@ typedef struct jpet_launch_info {
   int32_t row_cache;     /* pixels of a row held in registers between the two passes */
   int32_t events_per_batch;
   int32_t events_per_workgroup;
-  int32_t accumulator_bits; /* 64: 2^-32 fixed-point LDS accumulators; 32: 2^-24 ones (regions that
-                               do not fit otherwise); the image accumulator is 64-bit either way */
+  int32_t accumulator_bits; /* 64: 2^-32 fixed-point LDS accumulators; 32: 2^-23 ones (faster LDS
+                               atomics and smaller regions; the plan's cost model chooses); the
+                               image accumulator is 64-bit either way */
   double t_bin_width;    /* width of a tan(theta~) bin */
   int64_t lds_bytes;     /* dynamic LDS per workgroup */
   int64_t max_workgroups;/* launch grid of the event pass */

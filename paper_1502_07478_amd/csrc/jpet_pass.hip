@@ -236,7 +236,8 @@ __device__ __forceinline__ void copy_consts(const unsigned char* __restrict__ sr
 // pixel at column offset j of every lane's row falls into a different bank whatever the slant of
 // the ellipse.
 // One workgroup item.  GRAD = false: the MLEM event pass (acc: 2^-32 fixed-point image; the LDS
-// accumulators are 64-bit in 2^-32 units, or with ACC32 32-bit in 2^-24 units).
+// accumulators are 64-bit in 2^-32 units, or with ACC32 32-bit in 2^-acc_shift units, acc_shift = 23
+// for items of up to 511 events).
 // GRAD = true: the log-likelihood pass (acc: double image B = sum P / D; per-event log D' and the
 // sigma-derivative sums into red[0..2]; D' times the kernel's constant factor into D_out).
 template <int MAXLEN, int WAVES, bool GRAD, bool ACC32, int PITCH>
