@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define JPET_ABI_VERSION 2
+#define JPET_ABI_VERSION 3
 
 enum jpet_status {
   JPET_OK = 0,
@@ -64,7 +64,8 @@ enum jpet_status {
  * 0 < n_y, n_z <= 32768; n_y * pixel / 2 < R (every pixel centre lies between the strips);
  * kernel_variant in {0, 1}; 0 <= sigma_z_edge <= 1; gamma finite with
  * 2 gamma^2 < sigma_z,max^-2 sigma_dl^-2, sigma_z,max = sigma_z (1 + sigma_z_edge) (C^-1 of Eq. 12
- * positive definite for every event). */
+ * positive definite for every event); plan 0 or a code listed by jpet_mlem_plan_candidates for
+ * this geometry (a malformed code is JPET_EINVAL, one that does not fit JPET_EDOMAIN). */
 typedef struct jpet_geometry {
   double R;              /* strip half-separation: strips at y = +R and y = -R (Setup, Eq. 1) */
   double L;              /* strip length; strips span z in [-L/2, L/2] (Eq. 4) */
@@ -77,7 +78,11 @@ typedef struct jpet_geometry {
   int32_t n_z;           /* number of pixel columns (z) */
   int32_t kernel_variant;/* third component of a (Eq. 9): 0 as printed, 1 twice that (the
                             exact derivative of dl with respect to the emission angle) */
-  int32_t reserved;      /* must be 0 */
+  int32_t plan;          /* launch plan of the event pass: 0 lets the library's cost model choose;
+                            otherwise a plan code from jpet_mlem_plan_candidates (e.g. the one an
+                            autotuner timed fastest).  It changes how the work is laid out, not
+                            what is computed: results agree to FP32 rounding.  The workspace size,
+                            preparation and iterations of one event list must use the same value. */
   double sigma_z_edge;   /* sigma_z depending on the hit positions (Sec. 3, after Eq. 12): an event
                             with measured hits z_u, z_d takes, in both z slots of C^-1 and in its
                             3-sigma ellipse, sigma_z (1 + sigma_z_edge * zeta) with
@@ -180,6 +185,16 @@ int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, co
 int jpet_mlem_backproject(const jpet_geometry* g, const float* events, int64_t n, const float* rho, uint64_t* acc,
                           void* ws, size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream);
 
+/* The forward sums of the MLEM event pass: runs the pass of jpet_mlem_iterate (same plan and
+ * kernel, with the same workspace rules and flags) on the image rho and writes each event's
+ * denominator D_j = sum_{i in ellipse} P_ji rho_i (Sec. 4 listing, first loop; the denominator of
+ * Eq. 3), P including its constant factor, as that pass forms it (FP32 terms, double-precision
+ * sum of per-wavefront partials), rounded to float.  Dropped events get 0.  The pass's
+ * back-projection goes to the workspace's accumulator and is discarded.
+ *   D_out: device float [n], written entirely.  stats: as for jpet_mlem_iterate. */
+int jpet_mlem_denominators(const jpet_geometry* g, const float* events, int64_t n, const float* rho, float* D_out,
+                           void* ws, size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream);
+
 /* The pixel update of Eq. 3 (Eq. 5 with s NULL) from an accumulator filled by
  * jpet_mlem_backproject:  rho_l = acc_l 2^-32 / s_l where s_l > 0, else 0 (s NULL: acc_l 2^-32);
  * then acc_l = 0.
@@ -258,15 +273,30 @@ typedef struct jpet_launch_info {
   int32_t row_cache;     /* pixels of a row held in registers between the two passes */
   int32_t events_per_batch;
   int32_t events_per_workgroup;
-  int32_t accumulator_bits; /* 64: 2^-32 fixed-point LDS accumulators; 32: 2^-23 ones (faster LDS
-                               atomics and smaller regions; the plan's cost model chooses); the
-                               image accumulator is 64-bit either way */
+  int32_t accumulator_bits; /* 64: 2^-32 fixed-point LDS accumulators; 32: 2^-accumulator_shift
+                               ones, the shift set by the events per workgroup so that no slot can
+                               overflow (faster LDS atomics, smaller regions); the image
+                               accumulator is 64-bit in 2^-32 units either way */
   double t_bin_width;    /* width of a tan(theta~) bin */
   int64_t lds_bytes;     /* dynamic LDS per workgroup */
   int64_t max_workgroups;/* launch grid of the event pass */
+  int32_t plan;          /* the plan's code (what jpet_geometry.plan would name to get this plan) */
+  int32_t workgroups_per_cu; /* resident workgroups per CU the LDS region is sized for (0: generic) */
+  int32_t accumulator_shift; /* 32-bit accumulators: units of 2^-accumulator_shift counts; 0 for 64-bit
+                                ones (2^-32 units) */
+  int32_t pad;
 } jpet_launch_info;
 
 int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_info* info);
+
+/* Launch plans that fit the geometry for n_events events, sorted by the library's cost-model
+ * figure (ascending: the first is the one plan 0 selects).  pass: 0 for the MLEM event pass, 1 for
+ * the log-likelihood pass (whose plans use 64-bit accumulators only; sigma_mask as for
+ * jpet_loglik_grad, nullable).  g->plan is ignored.  Writes up to cap codes (and, if model_cost is
+ * not NULL, their figures) to the host arrays and the number of fitting plans to *count (host).
+ * A geometry whose ellipses fit no binned plan lists the generic pass's code (3) alone. */
+int jpet_mlem_plan_candidates(const jpet_geometry* g, int32_t pass, const double* sigma_mask, int64_t n_events,
+                              int32_t* codes, double* model_cost, int32_t cap, int32_t* count);
 
 /* Kernel timing.  While enabled (enable != 0), every launch of the MLEM event pass made by
  * jpet_mlem_iterate and jpet_mlem_backproject, and every iteration's group of event-pass launches

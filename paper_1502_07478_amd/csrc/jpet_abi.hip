@@ -85,7 +85,7 @@ int check_geometry(const jpet_geometry* g) {
     const double u = 1.0 / (szm * szm), w = 1.0 / (g->sigma_dl * g->sigma_dl);
     if (!(2.0 * g->gamma * g->gamma < u * w)) return JPET_EDOMAIN;
   }
-  if (g->reserved != 0) return JPET_EINVAL;
+  if (!plan_code_valid(g->plan)) return JPET_EINVAL;
   return JPET_OK;
 }
 
@@ -199,13 +199,16 @@ static void finish_plan(const jpet_geometry* g, int rows_max, int64_t n, Plan& p
   p.tiled = 1;
 }
 
-Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int force_waves, bool loglik) {
+void plan_candidates(const jpet_geometry* g, double msz, double mdl, int64_t n, bool loglik,
+                     std::vector<PlanCand>* out) {
+  out->clear();
   const bool allow_acc32 = !loglik;
   msz *= 1.0 + g->sigma_z_edge;  // the largest ellipse: sigma_z at the strip ends
   Plan none;
   memset(&none, 0, sizeof(none));
   none.ntb = 1;
   none.dt = 1.0;
+  none.code = kPlanGeneric;
   const double pix = g->pixel;
   const double hy_px = 1.5 * mdl / pix;                 // largest half height of an ellipse (rows)
   const double chord_px = 2.0 * 3.0 * msz / sqrt(2.0) / pix;  // longest chord along z (columns)
@@ -218,7 +221,10 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
       maxlen = c;
       break;
     }
-  if (maxlen == 0 || rows_max > 64 * 16) return none;  // generic pass
+  if (maxlen == 0 || rows_max > 64 * 16) {  // generic pass only
+    out->push_back({none, 0.0});
+    return;
+  }
   const int HY = (int)ceil(hy_px + 0.5) + 1;
   // Candidate regions: workgroups of 8 or 16 wavefronts, 1 to 4 of them resident per CU (their
   // LDS regions share the CU's 160 KB with the static batch buffers), 64-bit or 32-bit
@@ -227,7 +233,7 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
   // compiled for a register cache of 16/32/48/64 pixels keeps at most 8/6/5/4 wavefronts per SIMD
   // (its launch bounds guarantee that many).
   //
-  // The cheapest candidate under a simple cost model wins, in units of (event, pixel) pairs:
+  // Each candidate's cost-model figure, in units of (event, pixel) pairs:
   //   pairs of all events (an ellipse's area at theta = 0)
   //     x (4 / wavefronts per SIMD)^0.58  (measured: 6 resident wavefronts per SIMD run the pass
   //                                        in 0.79 of the time of 4)
@@ -245,14 +251,10 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
   // but three of 54,032 bytes do not (the pass then runs 27% slower), so a workgroup's LDS is
   // counted in whole 2 KB granules.
   const size_t kLdsPerCU = 160 * 1024, kStatic = loglik ? 8 * 1024 : 7 * 1024, kGranule = 2048;
-  const double dts[] = {0.0, 0.4, 0.2, 0.1, 0.05, 0.025};
-  const int tiles[] = {32, 24, 16, 12, 8};
   const double pairs_per_event = 3.14159265358979323846 * hy_px * (3.0 * msz / sqrt(2.0) / pix);
   const double nn = (double)(n > 0 ? n : 1);
-  Plan best = none;
-  double best_cost = 0.0;
   for (int waves : {8, 16}) {
-    if (rows_max > 64 * waves || (force_waves && waves != force_waves)) continue;
+    if (rows_max > 64 * waves) continue;
     for (int wgs = 1; wgs <= 4; ++wgs) {
       const int occ = wgs * waves / 4;  // resident wavefronts per SIMD
       if (occ > simd_waves) continue;
@@ -260,12 +262,14 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
       const double occ_factor = pow(4.0 / (double)occ, 0.58) * (waves == 16 ? 1.1 : 1.0);
       for (int acc32 = 0; acc32 <= 1; ++acc32) {
         if (acc32 && !allow_acc32) continue;
-        for (double dt : dts) {
+        for (int dti = 0; dti < kPlanDtCount; ++dti) {
+          const double dt = kPlanDt[dti];
           // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
           const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
           const double hz = 3.0 * sqrt(0.5 * msz * msz + 0.25 * mdl * mdl * tau * tau);
           const int HZ = (int)ceil(hz / pix + 1.0) + 1;
-          for (int T : tiles) {
+          for (int ti = 0; ti < kPlanTileCount; ++ti) {
+            const int T = kPlanTile[ti];
             // LDS: float image, then the accumulators, column-major with the row pitch rounded
             // up to the bank alignment; masked reads up to maxlen columns past the image must stay
             // in the accumulator array (W columns of 4 or 8 bytes)
@@ -287,6 +291,8 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
             p.RY = RY;
             p.W = W;
             p.lds_bytes = bytes;
+            p.wgs = wgs;
+            p.code = plan_code(waves, acc32, wgs, dti, ti);
             if (dt != 0.0) {
               p.ntb = (int)ceil(2.0 * tmax / dt);
               if (p.ntb < 1) p.ntb = 1;
@@ -297,16 +303,38 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, int fo
             const double items = nn / p.ev_per_wg + (nn < p.nbins ? nn : (double)p.nbins);
             const double cost = nn * pairs_per_event * occ_factor * (acc32 ? 0.82 : 1.0) +
                                 1.6 * items * (double)pitch * (double)W;
-            if (!best.tiled || cost < best_cost) {
-              best = p;
-              best_cost = cost;
-            }
+            out->push_back({p, cost});
           }
         }
       }
     }
   }
-  return best;
+  if (out->empty()) {
+    out->push_back({none, 0.0});
+    return;
+  }
+  std::stable_sort(out->begin(), out->end(), [](const PlanCand& a, const PlanCand& b) { return a.cost < b.cost; });
+}
+
+Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, bool loglik) {
+  std::vector<PlanCand> c;
+  plan_candidates(g, msz, mdl, n, loglik, &c);
+  const int32_t want = g->plan;
+  if (want == 0) return c[0].p;
+  if (want == kPlanGeneric) {
+    Plan p;
+    memset(&p, 0, sizeof(p));
+    p.ntb = 1;
+    p.dt = 1.0;
+    p.code = kPlanGeneric;
+    return p;
+  }
+  for (const PlanCand& x : c)
+    if (x.p.code == want) return x.p;
+  Plan bad = c[0].p;
+  bad.invalid = 1;
+  bad.code = want;
+  return bad;
 }
 
 size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Workspace* out) {
@@ -361,6 +389,7 @@ struct BatchLayout {
   std::vector<int64_t> begin;  // per instance: first workgroup in its group's grid
   int64_t max_npix = 0;
   size_t total = 0;
+  bool invalid = false;  // an instance names a plan that does not fit its geometry
 };
 
 BatchLayout batch_layout(const jpet_instance* inst, int count) {
@@ -374,6 +403,7 @@ BatchLayout batch_layout(const jpet_instance* inst, int count) {
     const jpet_geometry& g = inst[k].g;
     const Plan p = make_plan(&g, g.sigma_z, g.sigma_dl, inst[k].n);
     L.plan[k] = p;
+    if (p.invalid) L.invalid = true;
     // group key: generic instances last
     key[k] = p.tiled ? (p.maxlen * 100 + p.waves + (p.acc32 ? 10000 : 0)) : 1 << 30;
     if (p.tiled) {
@@ -459,11 +489,11 @@ static int timed(F launch, hipStream_t st) {
 }
 
 static int timed_event_pass(const Geo& geo, const Plan& p, int64_t n, const Workspace& w, const float* rho,
-                            hipStream_t st, int granularity = kPassPlanned) {
+                            hipStream_t st, int granularity = kPassPlanned, float* D_out = nullptr) {
   // per-pass counters: zero-denominator events, non-positive kappa pairs, unplaced rows
   hipError_t e = launch_fill_u64(w.cnt + C_ZERO_DEN, 2, st);
   if (e != hipSuccess) return hip_fail(e);
-  return timed([&] { return launch_event_pass(geo, p, n, w, rho, st, granularity); }, st);
+  return timed([&] { return launch_event_pass(geo, p, n, w, rho, st, granularity, D_out); }, st);
 }
 
 // The pass granularity a flag word asks for; -1 for unknown flags or both comparison flags.
@@ -480,7 +510,9 @@ const char* jpet_strerror(int status) {
   switch (status) {
     case JPET_OK: return "success";
     case JPET_EINVAL: return "invalid argument (NULL pointer, negative count or unknown flag)";
-    case JPET_EDOMAIN: return "argument out of domain (geometry, resolution or grid) or log-likelihood is -inf";
+    case JPET_EDOMAIN:
+      return "argument out of domain (geometry, resolution, grid, or a plan that does not fit them) or "
+             "log-likelihood is -inf";
     case JPET_EWORKSPACE: return "workspace missing, misaligned or smaller than jpet_mlem_workspace_size";
     case JPET_EHIP: return "HIP runtime error (see jpet_last_hip_error)";
     case JPET_ENOTSUP: return "not supported by this build";
@@ -531,6 +563,7 @@ int jpet_mlem_workspace_size(const jpet_geometry* g, int64_t n_events, size_t* b
   if (rc) return rc;
   if (!bytes || n_events < 0 || n_events > kMaxEvents) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n_events);
+  if (p.invalid) return JPET_EDOMAIN;  // the named plan does not fit this geometry
   *bytes = workspace_layout(p, n_events, npix_of(g), nullptr, nullptr);
   return JPET_OK;
 }
@@ -556,7 +589,8 @@ int jpet_loglik_workspace_size(const jpet_geometry* g, const double* sigma_mask,
     mdl = sigma_mask[1];
     if (!finite_pos(msz) || !finite_pos(mdl)) return JPET_EDOMAIN;
   }
-  const Plan p = make_plan(g, msz, mdl, n_events, 0, true);
+  const Plan p = make_plan(g, msz, mdl, n_events, true);
+  if (p.invalid) return JPET_EDOMAIN;  // the named plan does not fit this geometry
   *bytes = workspace_layout(p, n_events, npix_of(g), nullptr, nullptr);
   return JPET_OK;
 }
@@ -566,6 +600,7 @@ int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_
   if (rc) return rc;
   if (!info || n_events < 0 || n_events > kMaxEvents) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n_events);
+  if (p.invalid) return JPET_EDOMAIN;  // the named plan does not fit this geometry
   memset(info, 0, sizeof(*info));
   info->binned = p.tiled;
   info->tile_rows = p.TY;
@@ -582,6 +617,32 @@ int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_
   info->lds_bytes = (int64_t)p.lds_bytes;
   info->max_workgroups = p.max_items;
   info->accumulator_bits = p.tiled ? (p.acc32 ? 32 : 64) : 64;
+  info->plan = p.code;
+  info->workgroups_per_cu = p.tiled ? p.wgs : 0;
+  info->accumulator_shift = p.tiled && p.acc32 ? p.acc_shift : 0;
+  return JPET_OK;
+}
+
+int jpet_mlem_plan_candidates(const jpet_geometry* g, int32_t pass, const double* sigma_mask, int64_t n_events,
+                              int32_t* codes, double* model_cost, int32_t cap, int32_t* count) {
+  int rc = check_geometry(g);
+  if (rc) return rc;
+  if (!count || cap < 0 || (cap > 0 && !codes) || n_events < 0 || n_events > kMaxEvents) return JPET_EINVAL;
+  if (pass != 0 && pass != 1) return JPET_EINVAL;
+  if (pass == 0 && sigma_mask) return JPET_EINVAL;
+  double msz = g->sigma_z, mdl = g->sigma_dl;
+  if (sigma_mask) {
+    msz = sigma_mask[0];
+    mdl = sigma_mask[1];
+    if (!finite_pos(msz) || !finite_pos(mdl)) return JPET_EDOMAIN;
+  }
+  std::vector<PlanCand> c;
+  plan_candidates(g, msz, mdl, n_events, pass == 1, &c);
+  *count = (int32_t)c.size();
+  for (int32_t k = 0; k < cap && k < (int32_t)c.size(); ++k) {
+    codes[k] = c[k].p.code;
+    if (model_cost) model_cost[k] = c[k].cost;
+  }
   return JPET_OK;
 }
 
@@ -591,6 +652,7 @@ int jpet_mlem_prepare(const jpet_geometry* g, const float* events, int64_t n, vo
   if (rc) return rc;
   if (n < 0 || n > kMaxEvents || (n > 0 && !events)) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
+  if (p.invalid) return JPET_EDOMAIN;  // the named plan does not fit this geometry
   Workspace w;
   rc = carve(p, g, n, ws, ws_bytes, &w);
   if (rc) return rc;
@@ -606,6 +668,7 @@ int jpet_mlem_iterate(const jpet_geometry* g, const float* events, int64_t n, co
   const int gran = pass_granularity(flags);
   if (gran < 0) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
+  if (p.invalid) return JPET_EDOMAIN;  // the named plan does not fit this geometry
   Workspace w;
   rc = carve(p, g, n, ws, ws_bytes, &w);
   if (rc) return rc;
@@ -635,6 +698,7 @@ int jpet_mlem_backproject(const jpet_geometry* g, const float* events, int64_t n
   const int gran = pass_granularity(flags);
   if (gran < 0) return JPET_EINVAL;
   const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
+  if (p.invalid) return JPET_EDOMAIN;  // the named plan does not fit this geometry
   Workspace w;
   rc = carve(p, g, n, ws, ws_bytes, &w);
   if (rc) return rc;
@@ -647,6 +711,33 @@ int jpet_mlem_backproject(const jpet_geometry* g, const float* events, int64_t n
   w.acc = reinterpret_cast<unsigned long long*>(acc);
   rc = timed_event_pass(geo, p, n, w, rho, st, gran);
   if (rc) return rc;
+  if (stats) return read_stats(w, n, stats, st);
+  return JPET_OK;
+}
+
+int jpet_mlem_denominators(const jpet_geometry* g, const float* events, int64_t n, const float* rho, float* D_out,
+                           void* ws, size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream) {
+  int rc = check_geometry(g);
+  if (rc) return rc;
+  if (n < 0 || n > kMaxEvents || (n > 0 && !events) || !rho || (n > 0 && !D_out)) return JPET_EINVAL;
+  const int gran = pass_granularity(flags);
+  if (gran < 0) return JPET_EINVAL;
+  const Plan p = make_plan(g, g->sigma_z, g->sigma_dl, n);
+  if (p.invalid) return JPET_EDOMAIN;  // the named plan does not fit this geometry
+  Workspace w;
+  rc = carve(p, g, n, ws, ws_bytes, &w);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Geo geo = make_geo(g, g->sigma_z, g->sigma_dl);
+  if (!(flags & JPET_WS_PREPARED)) {
+    rc = do_prepare(geo, p, events, n, w, st);
+    if (rc) return rc;
+  }
+  hipError_t e = launch_fill_f32(D_out, n, st);
+  if (e != hipSuccess) return hip_fail(e);
+  rc = timed_event_pass(geo, p, n, w, rho, st, gran, D_out);
+  if (rc) return rc;
+  if ((e = launch_fill_u64(w.acc, npix_of(g), st)) != hipSuccess) return hip_fail(e);
   if (stats) return read_stats(w, n, stats, st);
   return JPET_OK;
 }
@@ -680,7 +771,8 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
   // a prepared workspace carries the kernel constants of the sigmas it was prepared with
   if ((flags & JPET_WS_PREPARED) && (msz != g->sigma_z || mdl != g->sigma_dl)) return JPET_EINVAL;
   // the binned log-likelihood pass accumulates doubles: plans with 64-bit region slots only
-  const Plan p = make_plan(g, msz, mdl, n, 0, true);
+  const Plan p = make_plan(g, msz, mdl, n, true);
+  if (p.invalid) return JPET_EDOMAIN;  // the named plan does not fit this geometry
   Workspace w;
   rc = carve(p, g, n, ws, ws_bytes, &w);
   if (rc) return rc;
@@ -706,7 +798,9 @@ int jpet_mlem_batched_workspace_size(const jpet_instance* inst, int32_t count, s
   if (!bytes) return JPET_EINVAL;
   const int rc = check_instances(inst, count);
   if (rc) return rc;
-  *bytes = batch_layout(inst, count).total;
+  const BatchLayout L = batch_layout(inst, count);
+  if (L.invalid) return JPET_EDOMAIN;
+  *bytes = L.total;
   return JPET_OK;
 }
 
@@ -715,6 +809,7 @@ static int batched_carve(const jpet_instance* inst, int32_t count, void* ws, siz
   int rc = check_instances(inst, count);
   if (rc) return rc;
   *L = batch_layout(inst, count);
+  if (L->invalid) return JPET_EDOMAIN;
   if (!ws || ((uintptr_t)ws & 255) != 0 || ws_bytes < L->total) return JPET_EWORKSPACE;
   w->resize(count);
   for (int k = 0; k < count; ++k) {

@@ -148,11 +148,11 @@ __device__ inline float kernel_fast(const RowK& r, float jf) {
   return rk * __builtin_amdgcn_exp2f(arg);
 }
 
-// The same with the kappa <= 0 case (P := 0) handled per pixel.
-__device__ inline float kernel_guarded(const RowK& r, float jf, bool* bad) {
+// The same with the kappa <= 0 case (P := 0) handled per pixel; such pixels are counted in nbad.
+__device__ inline float kernel_guarded(const RowK& r, float jf, int* nbad) {
   const float kap = fmaf(jf, r.dkap, r.kap0);
   if (!(kap > 0.0f)) {
-    *bad = true;
+    ++*nbad;
     return 0.0f;
   }
   return kernel_fast(r, jf);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "jpet.h"
 
 namespace jpet {
@@ -94,7 +96,31 @@ struct Plan {
   int64_t max_items;    // upper bound of workgroup items (the launch grid)
   int64_t max_batches;  // upper bound of batch blocks
   size_t lds_bytes;     // dynamic LDS of the tiled pass
+  int wgs;              // workgroups resident per CU the region was sized for
+  int32_t code;         // plan code (see plan_code_* below): what jpet_geometry.plan names
+  int invalid;          // 1: the requested code does not fit this geometry (JPET_EDOMAIN)
 };
+
+// Plan codes, the value of jpet_geometry.plan that names one plan: 0 lets the cost model choose;
+// otherwise bits 0-1 are the kind (1: binned pass with 8-wavefront workgroups, 2: with 16, 3: the
+// generic one-wavefront-per-event pass, all other bits 0), bit 2 selects 32-bit LDS
+// accumulators, bits 3-5 the workgroups resident per CU (1-4) the LDS region is sized for,
+// bits 6-8 the tan(theta~) bin width (index into kPlanDt) and bits 9-11 the square tile (index
+// into kPlanTile).
+constexpr int kPlanDtCount = 6, kPlanTileCount = 5;
+constexpr double kPlanDt[kPlanDtCount] = {0.0, 0.4, 0.2, 0.1, 0.05, 0.025};
+constexpr int kPlanTile[kPlanTileCount] = {32, 24, 16, 12, 8};
+constexpr int32_t kPlanGeneric = 3;
+inline int32_t plan_code(int waves, int acc32, int wgs, int dt_index, int tile_index) {
+  return (waves == 16 ? 2 : 1) | (acc32 ? 4 : 0) | (wgs << 3) | (dt_index << 6) | (tile_index << 9);
+}
+// 1 when the code is well formed (not whether it fits a geometry)
+inline bool plan_code_valid(int32_t c) {
+  if (c == 0 || c == kPlanGeneric) return true;
+  const int kind = c & 3, wgs = (c >> 3) & 7, dti = (c >> 6) & 7, ti = (c >> 9) & 7;
+  return kind >= 1 && kind <= 2 && wgs >= 1 && wgs <= 4 && dti < kPlanDtCount && ti < kPlanTileCount &&
+         (c >> 12) == 0;
+}
 
 // Counters kept in the workspace (unsigned 64-bit).
 enum Counter {
@@ -161,11 +187,20 @@ static_assert(sizeof(InstWrite) <= 4096, "InstWrite is passed by value as a kern
 constexpr int RED_SLOTS = 4096;
 constexpr uint32_t kNoBin = 0xffffffffu;
 
-// force_waves: 0 = choose; 8 or 16 = only plans with that many wavefronts per workgroup.
-// loglik: plan for the log-likelihood pass (64-bit region slots for its doubles, its own register
-// budget) instead of the MLEM pass.
-Plan make_plan(const jpet_geometry* g, double mask_sz, double mask_sdl, int64_t n, int force_waves = 0,
-               bool loglik = false);
+// The plan of a pass: the one g->plan names, or with g->plan = 0 the cheapest candidate under the
+// cost model.  loglik: plan for the log-likelihood pass (64-bit region slots for its doubles, its
+// own register budget) instead of the MLEM pass.  A named plan that does not fit the geometry
+// comes back with invalid = 1.
+Plan make_plan(const jpet_geometry* g, double mask_sz, double mask_sdl, int64_t n, bool loglik = false);
+
+// Every binned plan that fits the geometry, with its cost-model figure (lower is faster), sorted
+// by that figure; the generic pass is listed last when no binned plan fits.
+struct PlanCand {
+  Plan p;
+  double cost;
+};
+void plan_candidates(const jpet_geometry* g, double mask_sz, double mask_sdl, int64_t n, bool loglik,
+                     std::vector<PlanCand>* out);
 size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Workspace* out);
 
 // Kernel launchers (return the hipError_t of the launch).
@@ -177,8 +212,11 @@ hipError_t launch_prepare(const Geo& g, const Plan& p, const float* events, int6
 // Work split of the event pass: the plan's (binned when tiled), or for comparison one wavefront
 // per event (the generic pass) or one thread per event.
 constexpr int kPassPlanned = 0, kPassWavePerEvent = 1, kPassThreadPerEvent = 2;
+// D_out (nullable): each event's denominator, with P's constant factor, at its input position
+// (events that are dropped are not written).
 hipError_t launch_event_pass(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
-                             hipStream_t st, int granularity = kPassPlanned);
+                             hipStream_t st, int granularity = kPassPlanned, float* D_out = nullptr);
+hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_update(const Geo& g, const float* s, float* rho, const Workspace& ws, hipStream_t st);
 // batched: table of count instances in device memory; grid = total workgroups of the tiled ones
 hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t st);

@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) k_loglik_pass(Geo g, int64_t n, const Eve
       if (D_out && lane == 0) D_out[j] = 0.0f;
       continue;
     }
-    bool bad = false;
+    int nbad = 0;  // pixels of this lane's row with kappa <= 0 (P := 0)
     float D = 0.0f, Du = 0.0f, Dw = 0.0f;
     for (int b0 = e.r0; b0 <= e.r1; b0 += WAVE) {
       const int i = b0 + lane;
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(256) k_loglik_pass(Geo g, int64_t n, const Eve
         const float* rr = rho + (int64_t)i * g.n_z;
         for (int k = klo; k <= khi; ++k) {
           const float jf = (float)(k - klo);
-          const float m = kernel_guarded(r, jf, &bad) * rr[k];
+          const float m = kernel_guarded(r, jf, &nbad) * rr[k];
           float du, dw;
           dlogp(rg, jf, &du, &dw);
           D += m;
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256) k_loglik_pass(Geo g, int64_t n, const Eve
     D = wave_sum(D);
     Du = wave_sum(Du);
     Dw = wave_sum(Dw);
-    nbad_tot += wave_sum_u64(bad ? 1ull : 0ull);
+    nbad_tot += wave_sum_u64((unsigned long long)nbad);
     if (D_out && lane == 0) D_out[j] = D * norm;
     if (!(D > 0.0f)) {
       nzero += 1;
@@ -170,9 +170,9 @@ __global__ void __launch_bounds__(256) k_loglik_pass(Geo g, int64_t n, const Eve
           double kf, ks;
           const RowK r = row_constants(g, e, i, klo, &kf, &ks);
           double* bb = B + (int64_t)i * g.n_z;
-          bool dummy = false;
+          int again = 0;  // recomputed values: not counted twice
           for (int k = klo; k <= khi; ++k) {
-            const float pv = kernel_guarded(r, (float)(k - klo), &dummy);
+            const float pv = kernel_guarded(r, (float)(k - klo), &again);
             if (pv != 0.0f) unsafeAtomicAdd(&bb[k], (double)pv * invD);
           }
         }
@@ -257,6 +257,12 @@ hipError_t launch_direct_image(const Geo& g, double L, const float* events, int6
   const int64_t npix = (int64_t)g.n_y * g.n_z;
   hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(npix, 256)), dim3(256), 0, st, img, npix);
   if (n > 0) hipLaunchKernelGGL(k_direct_image, dim3(grid_for(n, 256)), dim3(256), 0, st, g, L, events, n, img);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ struct RowF {
 // mask; idle lanes carry row constants that make every kernel value 0.
 template <int MAXLEN, bool GUARD>
 __device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __restrict__ rho_s, int base, int pitch,
-                                       int len, int wmin, int wl, float (&m)[MAXLEN], bool* bad) {
+                                       int len, int wmin, int wl, float (&m)[MAXLEN], int* nbad) {
   float D = 0.0f;
   const float* const rr = rho_s + base;  // the row's first pixel
 #pragma unroll
@@ -79,7 +79,7 @@ __device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __
           float kap = fmaf(jf, rk.dkap, rk.kap0);
           bool keep = j < len;
           if (GUARD && !(kap > 0.0f)) {
-            if (keep) *bad = true;
+            if (keep) ++*nbad;
             keep = false;
             kap = 1.0f;
           }
@@ -150,7 +150,7 @@ struct GradShared {
 template <int MAXLEN, bool GUARD>
 __device__ __forceinline__ void pass1g(const RowF& rk, const RowD& rd, float qa, float pixf, float cu, float irs,
                                        const float* __restrict__ rho_s, int base, int pitch, int len, int wmin,
-                                       int wl, float (&m)[MAXLEN], bool* bad, float& D, float& Du, float& Dw) {
+                                       int wl, float (&m)[MAXLEN], int* nbad, float& D, float& Du, float& Dw) {
   D = 0.0f;
   Du = 0.0f;
   Dw = 0.0f;
@@ -168,7 +168,7 @@ __device__ __forceinline__ void pass1g(const RowF& rk, const RowD& rd, float qa,
         float kap = fmaf(jf, rk.dkap, rk.kap0);
         bool keep = full || j < len;
         if (GUARD && !(kap > 0.0f)) {
-          if (keep) *bad = true;
+          if (keep) ++*nbad;
           keep = false;
           kap = 1.0f;
         }
@@ -184,8 +184,10 @@ __device__ __forceinline__ void pass1g(const RowF& rk, const RowD& rd, float qa,
         const float h = fmaf(gk, gk, rq * rq);
         const float du = fmaf(-Kzh, h, fmaf(gk, Gz, fmaf(-b1, b1, cu)));
         const float dw = fmaf(-rd.Klh, h, fmaf(gk, rd.Gl, rd.cw));
+        // masked reads past the row's end may land in the region's double accumulators, whose
+        // low words can be any bit pattern (NaN included): select, do not multiply by 0
         const float pk = keep ? pv : 0.0f;
-        const float v = pk * r[jj];
+        const float v = keep ? pv * r[jj] : 0.0f;
         m[j] = pk;
         D += v;
         Du = fmaf(v, du, Du);
@@ -238,6 +240,8 @@ __device__ __forceinline__ void copy_consts(const unsigned char* __restrict__ sr
 // One workgroup item.  GRAD = false: the MLEM event pass (acc: 2^-32 fixed-point image; the LDS
 // accumulators are 64-bit in 2^-32 units, or with ACC32 32-bit in 2^-acc_shift units, acc_shift = 23
 // for items of up to 511 events).
+// With D_out (MLEM mode) each event's denominator times the kernel's constant factor is also
+// written at the event's input position (evs: the bin-sorted records).
 // GRAD = true: the log-likelihood pass (acc: double image B = sum P / D; per-event log D' and the
 // sigma-derivative sums into red[0..2]; D' times the kernel's constant factor into D_out).
 template <int MAXLEN, int WAVES, bool GRAD, bool ACC32, int PITCH>
@@ -246,7 +250,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
                                                 unsigned long long* __restrict__ acc,
                                                 unsigned long long* __restrict__ cnt, unsigned char* smem,
                                                 PassShared& ps, GradShared* gsh, float* __restrict__ D_out,
-                                                double* __restrict__ red) {
+                                                double* __restrict__ red, const EventRec* __restrict__ evs) {
   // rows of a column in LDS; a compile-time pitch turns the per-pixel LDS addresses into
   // immediate offsets
   const int pitch = PITCH ? PITCH : p.pitch;
@@ -373,6 +377,9 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
         }
         const int nbp = min(p.ev_per_batch, it.count - (bi - 1) * p.ev_per_batch);
         if (tid < nbp && !(Dp[tid] > 0.0)) atomicAdd(&ps.zero, 1u);
+        // the denominators themselves (with P's constant factor), by input position
+        if (D_out && tid < nbp)
+          D_out[evs[it.start + (bi - 1) * p.ev_per_batch + tid].index] = (float)(Dp[tid] * g.cnorm);
       }
     }
     if (bi < nbatch) {
@@ -433,22 +440,22 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       }
 
       // pass 1: m = P rho along the row (log-likelihood mode: m = P), D partial sums
-      bool bad = false;
+      int nbad = 0;  // pixels of this thread's row with kappa <= 0 (P := 0)
       float D, Du = 0.0f, Dw = 0.0f;
       if constexpr (GRAD) {
         if (__any(!safe)) {
-          pass1g<MAXLEN, true>(rk, rd, qa, pixf, cuf, irs, rho_s, base, pitch, len, wn, wl, m, &bad, D, Du, Dw);
+          pass1g<MAXLEN, true>(rk, rd, qa, pixf, cuf, irs, rho_s, base, pitch, len, wn, wl, m, &nbad, D, Du, Dw);
         } else {
-          pass1g<MAXLEN, false>(rk, rd, qa, pixf, cuf, irs, rho_s, base, pitch, len, wn, wl, m, &bad, D, Du, Dw);
+          pass1g<MAXLEN, false>(rk, rd, qa, pixf, cuf, irs, rho_s, base, pitch, len, wn, wl, m, &nbad, D, Du, Dw);
         }
       } else {
         if (__any(!safe)) {
-          D = pass1<MAXLEN, true>(rk, rk.qa, rho_s, base, pitch, len, wn, wl, m, &bad);
+          D = pass1<MAXLEN, true>(rk, rk.qa, rho_s, base, pitch, len, wn, wl, m, &nbad);
         } else {
-          D = pass1<MAXLEN, false>(rk, rk.qa, rho_s, base, pitch, len, wn, wl, m, &bad);
+          D = pass1<MAXLEN, false>(rk, rk.qa, rho_s, base, pitch, len, wn, wl, m, &nbad);
         }
       }
-      if (bad) atomicAdd(&ps.bad, 1u);
+      if (nbad) atomicAdd(&ps.bad, (unsigned)nbad);
 
       // per-event denominators: segmented reduction over the wavefront's rows
       double* Dc = ps.D[bi % 3];
@@ -538,12 +545,14 @@ __global__ void __launch_bounds__(WAVES * 64, pass_waves_per_simd<MAXLEN>()) k_e
                                                                     const BinItem* __restrict__ items,
                                                                     const float* __restrict__ rho,
                                                                     unsigned long long* __restrict__ acc,
-                                                                    unsigned long long* __restrict__ cnt) {
+                                                                    unsigned long long* __restrict__ cnt,
+                                                                    const EventRec* __restrict__ evs,
+                                                                    float* __restrict__ D_out) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ PassShared ps;
   if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
   event_pass_item<MAXLEN, WAVES, false, ACC32, PITCH>(g, p, blocks, items[blockIdx.x], rho, acc, cnt, smem, ps,
-                                                     nullptr, nullptr, nullptr);
+                                                     nullptr, D_out, nullptr, evs);
 }
 
 // The log-likelihood pass on the binned layout (B: double image of sum P / D, zeroed by the
@@ -560,7 +569,7 @@ __global__ void __launch_bounds__(WAVES * 64, MAXLEN <= 16 ? 5 : 4) k_loglik_til
   if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
   event_pass_item<MAXLEN, WAVES, true, false, 0>(g, p, blocks, items[blockIdx.x], rho,
                                                 reinterpret_cast<unsigned long long*>(B), cnt, smem, ps, &gsh, D_out,
-                                                red);
+                                                red, nullptr);
 }
 
 // The same pass over many independent reconstructions in one launch: the grid is the
@@ -582,7 +591,7 @@ __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_batched(const Batc
   const int64_t local = b - I.item_begin;
   if (!I.tiled || local >= (int64_t)I.cnt[C_ITEMS]) return;
   event_pass_item<MAXLEN, WAVES, false, ACC32, 0>(I.g, I.p, I.blocks, I.items[local], I.rho, I.acc, I.cnt, smem, ps,
-                                                 nullptr, nullptr, nullptr);
+                                                 nullptr, nullptr, nullptr, nullptr);
 }
 
 // Generic pass for geometries whose rows or regions do not fit the tiled pass: one wavefront per
@@ -590,13 +599,14 @@ __global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_batched(const Batc
 __global__ void __launch_bounds__(256) k_event_pass_generic(Geo g, int64_t n, const EventRec* __restrict__ ev,
                                                             const float* __restrict__ rho,
                                                             unsigned long long* __restrict__ acc,
-                                                            unsigned long long* __restrict__ cnt) {
+                                                            unsigned long long* __restrict__ cnt,
+                                                            float* __restrict__ D_out) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t j = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
   if (j >= n) return;
   const EventRec e = ev[j];
   if (e.r1 < e.r0) return;
-  bool bad = false;
+  int nbad = 0;  // pixels of this lane's row with kappa <= 0 (P := 0)
   float D = 0.0f;
   for (int b0 = e.r0; b0 <= e.r1; b0 += WAVE) {
     const int i = b0 + lane;
@@ -605,12 +615,14 @@ __global__ void __launch_bounds__(256) k_event_pass_generic(Geo g, int64_t n, co
       double kf, ks;
       const RowK r = row_constants(g, e, i, klo, &kf, &ks);
       const float* rr = rho + (int64_t)i * g.n_z;
-      for (int k = klo; k <= khi; ++k) D += kernel_guarded(r, (float)(k - klo), &bad) * rr[k];
+      for (int k = klo; k <= khi; ++k) D += kernel_guarded(r, (float)(k - klo), &nbad) * rr[k];
     }
   }
   D = wave_sum(D);
-  const unsigned long long nbad = wave_sum_u64(bad ? 1ull : 0ull);
-  if (lane == 0 && nbad) atomicAdd(&cnt[C_KAPPA_BAD], nbad);
+  const unsigned long long nbad_w = wave_sum_u64((unsigned long long)nbad);
+  if (lane == 0 && nbad_w) atomicAdd(&cnt[C_KAPPA_BAD], nbad_w);
+  int again = 0;  // pass 2 recomputes the same values: not counted twice
+  if (lane == 0 && D_out) D_out[j] = (float)((double)D * g.cnorm);
   if (!(D > 0.0f)) {
     if (lane == 0) atomicAdd(&cnt[C_ZERO_DEN], 1ull);
     return;
@@ -625,7 +637,7 @@ __global__ void __launch_bounds__(256) k_event_pass_generic(Geo g, int64_t n, co
       const float* rr = rho + (int64_t)i * g.n_z;
       unsigned long long* aa = acc + (int64_t)i * g.n_z;
       for (int k = klo; k <= khi; ++k) {
-        const float m = kernel_guarded(r, (float)(k - klo), &bad) * rr[k];
+        const float m = kernel_guarded(r, (float)(k - klo), &again) * rr[k];
         if (m > 0.0f) atomicAdd(&aa[k], (unsigned long long)(unsigned)fmaf(m, sc, 0.5f));
       }
     }
@@ -639,12 +651,13 @@ __global__ void __launch_bounds__(256) k_event_pass_generic(Geo g, int64_t n, co
 __global__ void __launch_bounds__(256) k_event_pass_thread(Geo g, int64_t n, const EventRec* __restrict__ ev,
                                                            const float* __restrict__ rho,
                                                            unsigned long long* __restrict__ acc,
-                                                           unsigned long long* __restrict__ cnt) {
+                                                           unsigned long long* __restrict__ cnt,
+                                                           float* __restrict__ D_out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const EventRec e = ev[j];
   if (e.r1 < e.r0) return;
-  bool bad = false;
+  int nbad = 0;  // pixels of this event with kappa <= 0 (P := 0)
   float D = 0.0f;
   for (int i = e.r0; i <= e.r1; ++i) {
     int klo, khi;
@@ -652,9 +665,11 @@ __global__ void __launch_bounds__(256) k_event_pass_thread(Geo g, int64_t n, con
     double kf, ks;
     const RowK r = row_constants(g, e, i, klo, &kf, &ks);
     const float* rr = rho + (int64_t)i * g.n_z;
-    for (int k = klo; k <= khi; ++k) D += kernel_guarded(r, (float)(k - klo), &bad) * rr[k];
+    for (int k = klo; k <= khi; ++k) D += kernel_guarded(r, (float)(k - klo), &nbad) * rr[k];
   }
-  if (bad) atomicAdd(&cnt[C_KAPPA_BAD], 1ull);
+  if (nbad) atomicAdd(&cnt[C_KAPPA_BAD], (unsigned long long)nbad);
+  int again = 0;  // pass 2 recomputes the same values: not counted twice
+  if (D_out) D_out[j] = (float)((double)D * g.cnorm);
   if (!(D > 0.0f)) {
     atomicAdd(&cnt[C_ZERO_DEN], 1ull);
     return;
@@ -668,7 +683,7 @@ __global__ void __launch_bounds__(256) k_event_pass_thread(Geo g, int64_t n, con
     const float* rr = rho + (int64_t)i * g.n_z;
     unsigned long long* aa = acc + (int64_t)i * g.n_z;
     for (int k = klo; k <= khi; ++k) {
-      const float m = kernel_guarded(r, (float)(k - klo), &bad) * rr[k];
+      const float m = kernel_guarded(r, (float)(k - klo), &again) * rr[k];
       if (m > 0.0f) atomicAdd(&aa[k], (unsigned long long)(unsigned)fmaf(m, sc, 0.5f));
     }
   }
@@ -692,14 +707,15 @@ __global__ void k_update(int64_t npix, const float* __restrict__ s, float* __res
 }
 
 template <int MAXLEN, int WAVES, bool ACC32>
-hipError_t launch_tiled(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, hipStream_t st) {
+hipError_t launch_tiled(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, float* D_out,
+                        hipStream_t st) {
   auto kern = p.pitch == 128   ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 128>
               : p.pitch == 256 ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 256>
                                : k_event_pass_tiled<MAXLEN, WAVES, ACC32, 0>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)p.max_items), dim3(64 * p.waves), p.lds_bytes, st, g, p, ws.batches,
-                     ws.items, rho, ws.acc, ws.cnt);
+                     ws.items, rho, ws.acc, ws.cnt, ws.evs, D_out);
   return hipGetLastError();
 }
 
@@ -816,37 +832,39 @@ hipError_t launch_update_batched(const BatchInst* table, int count, int64_t max_
 }
 
 hipError_t launch_event_pass(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
-                             hipStream_t st, int granularity) {
+                             hipStream_t st, int granularity, float* D_out) {
   if (n <= 0) return hipSuccess;
   if (granularity == kPassThreadPerEvent) {
     const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_event_pass_thread, dim3((unsigned)blocks), dim3(256), 0, st, g, n, ws.ev, rho, ws.acc, ws.cnt);
+    hipLaunchKernelGGL(k_event_pass_thread, dim3((unsigned)blocks), dim3(256), 0, st, g, n, ws.ev, rho, ws.acc, ws.cnt,
+                       D_out);
     return hipGetLastError();
   }
   if (p.tiled && granularity == kPassPlanned) {
     const int key = p.maxlen * 100 + p.waves + (p.acc32 ? 10000 : 0);
     switch (key) {
-      case 1608: return launch_tiled<16, 8, false>(g, p, ws, rho, st);
-      case 3208: return launch_tiled<32, 8, false>(g, p, ws, rho, st);
-      case 4808: return launch_tiled<48, 8, false>(g, p, ws, rho, st);
-      case 6408: return launch_tiled<64, 8, false>(g, p, ws, rho, st);
-      case 1616: return launch_tiled<16, 16, false>(g, p, ws, rho, st);
-      case 3216: return launch_tiled<32, 16, false>(g, p, ws, rho, st);
-      case 4816: return launch_tiled<48, 16, false>(g, p, ws, rho, st);
-      case 6416: return launch_tiled<64, 16, false>(g, p, ws, rho, st);
-      case 11608: return launch_tiled<16, 8, true>(g, p, ws, rho, st);
-      case 13208: return launch_tiled<32, 8, true>(g, p, ws, rho, st);
-      case 14808: return launch_tiled<48, 8, true>(g, p, ws, rho, st);
-      case 16408: return launch_tiled<64, 8, true>(g, p, ws, rho, st);
-      case 11616: return launch_tiled<16, 16, true>(g, p, ws, rho, st);
-      case 13216: return launch_tiled<32, 16, true>(g, p, ws, rho, st);
-      case 14816: return launch_tiled<48, 16, true>(g, p, ws, rho, st);
-      case 16416: return launch_tiled<64, 16, true>(g, p, ws, rho, st);
+      case 1608: return launch_tiled<16, 8, false>(g, p, ws, rho, D_out, st);
+      case 3208: return launch_tiled<32, 8, false>(g, p, ws, rho, D_out, st);
+      case 4808: return launch_tiled<48, 8, false>(g, p, ws, rho, D_out, st);
+      case 6408: return launch_tiled<64, 8, false>(g, p, ws, rho, D_out, st);
+      case 1616: return launch_tiled<16, 16, false>(g, p, ws, rho, D_out, st);
+      case 3216: return launch_tiled<32, 16, false>(g, p, ws, rho, D_out, st);
+      case 4816: return launch_tiled<48, 16, false>(g, p, ws, rho, D_out, st);
+      case 6416: return launch_tiled<64, 16, false>(g, p, ws, rho, D_out, st);
+      case 11608: return launch_tiled<16, 8, true>(g, p, ws, rho, D_out, st);
+      case 13208: return launch_tiled<32, 8, true>(g, p, ws, rho, D_out, st);
+      case 14808: return launch_tiled<48, 8, true>(g, p, ws, rho, D_out, st);
+      case 16408: return launch_tiled<64, 8, true>(g, p, ws, rho, D_out, st);
+      case 11616: return launch_tiled<16, 16, true>(g, p, ws, rho, D_out, st);
+      case 13216: return launch_tiled<32, 16, true>(g, p, ws, rho, D_out, st);
+      case 14816: return launch_tiled<48, 16, true>(g, p, ws, rho, D_out, st);
+      case 16416: return launch_tiled<64, 16, true>(g, p, ws, rho, D_out, st);
       default: return hipErrorInvalidValue;
     }
   }
   const int64_t blocks = (n + 3) / 4;
-  hipLaunchKernelGGL(k_event_pass_generic, dim3((unsigned)blocks), dim3(256), 0, st, g, n, ws.ev, rho, ws.acc, ws.cnt);
+  hipLaunchKernelGGL(k_event_pass_generic, dim3((unsigned)blocks), dim3(256), 0, st, g, n, ws.ev, rho, ws.acc, ws.cnt,
+                     D_out);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ class Geometry(ctypes.Structure):
         ("R", ctypes.c_double), ("L", ctypes.c_double), ("sigma_z", ctypes.c_double),
         ("sigma_dl", ctypes.c_double), ("gamma", ctypes.c_double), ("pixel", ctypes.c_double),
         ("n_y", ctypes.c_int32), ("n_z", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("sigma_z_edge", ctypes.c_double),
+        ("plan", ctypes.c_int32), ("sigma_z_edge", ctypes.c_double),
     ]
 
     @property
@@ -58,7 +58,9 @@ class LaunchInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "binned", "tile_rows", "tile_cols", "halo_rows", "halo_cols", "t_bins", "bins", "waves", "row_cache",
         "events_per_batch", "events_per_workgroup", "accumulator_bits")] + [
-        ("t_bin_width", ctypes.c_double), ("lds_bytes", ctypes.c_int64), ("max_workgroups", ctypes.c_int64)]
+        ("t_bin_width", ctypes.c_double), ("lds_bytes", ctypes.c_int64), ("max_workgroups", ctypes.c_int64),
+        ("plan", ctypes.c_int32), ("workgroups_per_cu", ctypes.c_int32), ("accumulator_shift", ctypes.c_int32),
+        ("pad", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -100,6 +102,10 @@ def _lib():
         L.jpet_mlem_batched_prepare.argtypes = [ip, i32, vp, sz, vp]
         L.jpet_mlem_batched_iterate.argtypes = [ip, i32, i32, vp, sz, u32, sp, vp]
         L.jpet_mlem_launch_info.argtypes = [gp, i64, ctypes.POINTER(LaunchInfo)]
+        L.jpet_mlem_plan_candidates.argtypes = [gp, i32, ctypes.POINTER(ctypes.c_double), i64,
+                                                ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), i32,
+                                                ctypes.POINTER(i32)]
+        L.jpet_mlem_denominators.argtypes = [gp, vp, i64, vp, vp, vp, sz, u32, sp, vp]
         L.jpet_profile_enable.argtypes = [ctypes.c_int]
         L.jpet_profile_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
         _L = L
@@ -112,10 +118,17 @@ def lib():
 
 
 def geometry(R, L, sigma_z, sigma_dl, pixel, n_y, n_z, kernel_variant=0, gamma=0.0,
-             sigma_z_edge=0.0) -> Geometry:
-    """sigma_z_edge: relative rise of sigma_z from the strip centre to its ends (0: constant)."""
+             sigma_z_edge=0.0, plan=0) -> Geometry:
+    """sigma_z_edge: relative rise of sigma_z from the strip centre to its ends (0: constant).
+    plan: 0 (the library's cost model chooses) or a code from plan_candidates."""
     return Geometry(float(R), float(L), float(sigma_z), float(sigma_dl), float(gamma), float(pixel), int(n_y),
-                    int(n_z), int(kernel_variant), 0, float(sigma_z_edge))
+                    int(n_z), int(kernel_variant), int(plan), float(sigma_z_edge))
+
+
+def with_plan(g: Geometry, plan: int) -> Geometry:
+    """A copy of g that names the given plan code."""
+    return Geometry(g.R, g.L, g.sigma_z, g.sigma_dl, g.gamma, g.pixel, g.n_y, g.n_z, g.kernel_variant, int(plan),
+                    g.sigma_z_edge)
 
 
 def _stream(stream=None):
@@ -180,6 +193,17 @@ def launch_info(g: Geometry, n_events: int) -> dict:
     return info.as_dict()
 
 
+def plan_candidates(g: Geometry, n_events: int, loglik: bool = False, sigma_mask=None, cap: int = 1024):
+    """[(plan code, cost-model figure)] of the plans that fit, cheapest first (jpet_mlem_plan_candidates)."""
+    codes = (ctypes.c_int32 * cap)()
+    cost = (ctypes.c_double * cap)()
+    count = ctypes.c_int32(0)
+    sm = (ctypes.c_double * 2)(*sigma_mask) if sigma_mask is not None else None
+    _check(_lib().jpet_mlem_plan_candidates(ctypes.byref(g), 1 if loglik else 0, sm, int(n_events), codes, cost, cap,
+                                            ctypes.byref(count)), "jpet_mlem_plan_candidates")
+    return [(int(codes[k]), float(cost[k])) for k in range(min(cap, count.value))]
+
+
 def workspace(g: Geometry, n_events: int, device=None) -> torch.Tensor:
     return torch.empty(workspace_size(g, n_events), dtype=torch.uint8, device=device or "cuda")
 
@@ -231,6 +255,24 @@ def mlem(events: torch.Tensor, g: Geometry, n_iter: int, sens: torch.Tensor | No
         rho = rho0.clone()
     mlem_iterate(g, events, rho, n_iter, s=sens)
     return rho
+
+
+def denominators(g: Geometry, events: torch.Tensor, rho: torch.Tensor, ws: torch.Tensor | None = None,
+                 prepared: bool = False, want_stats: bool = False, stream=None, split: str | None = None):
+    """Per-event forward sums D_j of the MLEM event pass at rho (jpet_mlem_denominators): a float32
+    [n] tensor (0 for dropped events), and the stats dict when want_stats."""
+    _events(events)
+    _need(rho, "rho", torch.float32, g.shape)
+    if ws is None:
+        ws = workspace(g, events.shape[0], rho.device)
+        prepared = False
+    D = torch.empty(events.shape[0], dtype=torch.float32, device=rho.device)
+    st = Stats() if want_stats else None
+    rc = _lib().jpet_mlem_denominators(ctypes.byref(g), _ptr(events), events.shape[0], _ptr(rho), _ptr(D), _ptr(ws),
+                                       ws.numel(), (JPET_WS_PREPARED if prepared else 0) | _SPLIT[split],
+                                       ctypes.byref(st) if st is not None else None, _stream(stream))
+    _check(rc, "jpet_mlem_denominators")
+    return (D, st.as_dict()) if want_stats else D
 
 
 def accumulator(g: Geometry, device=None) -> torch.Tensor:
@@ -433,7 +475,9 @@ def loglik_grad(g: Geometry, events: torch.Tensor, rho: torch.Tensor, s: torch.T
     rc = _lib().jpet_loglik_grad(ctypes.byref(g), sm, _ptr(events), n, _ptr(s), _ptr(rho), _ptr(out3), _ptr(gr),
                                  _ptr(D), _ptr(ws), ws.numel(), JPET_WS_PREPARED if prepared else 0,
                                  ctypes.byref(st) if st is not None else None, _stream(stream))
-    if rc != JPET_EDOMAIN:
+    # JPET_EDOMAIN after the pass means a valid event has D = 0 (l = -inf, reported through stats);
+    # before it (a geometry or mask out of domain) nothing was written, which is an error
+    if not (rc == JPET_EDOMAIN and st is not None and st.n_zero_denominator > 0):
         _check(rc, "jpet_loglik_grad")
     return LogLik(out3, gr, D, st.as_dict() if st is not None else None)
 
@@ -456,7 +500,7 @@ class JPetLogLik(torch.autograd.Function):
     def forward(ctx, rho, sigma_z, sigma_dl, events, g, s=None, sigma_mask=None):
         sz = float(sigma_z)
         sd = float(sigma_dl)
-        gg = Geometry(g.R, g.L, sz, sd, g.gamma, g.pixel, g.n_y, g.n_z, g.kernel_variant, 0, g.sigma_z_edge)
+        gg = Geometry(g.R, g.L, sz, sd, g.gamma, g.pixel, g.n_y, g.n_z, g.kernel_variant, g.plan, g.sigma_z_edge)
         mask = (sz, sd) if sigma_mask is None else tuple(float(x) for x in sigma_mask)
         res = loglik_grad(gg, events, rho.detach().contiguous(), s=s, sigma_mask=mask,
                           want_grad_rho=ctx.needs_input_grad[0])

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_strerror(lib):
-    assert lib.jpet_abi_version() == 2
+    assert lib.jpet_abi_version() == 3
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.jpet_strerror(code)
     assert lib.jpet_strerror(-99) == b"unknown status"
@@ -148,6 +148,60 @@ def test_entry_points_reject_bad_arguments_before_any_device_work(lib):
     assert lib.jpet_mlem_update(gp, None, None, fake, None) == jpet.JPET_EINVAL
     assert lib.jpet_mlem_update(gp, None, fake, None, None) == jpet.JPET_EINVAL
     assert lib.jpet_mlem_update(None, None, fake, fake, None) == jpet.JPET_EINVAL
+
+
+def test_denominators_validation(lib):
+    g = jpet.geometry(**GOOD)
+    gp = ctypes.byref(g)
+    fake = ctypes.c_void_p(0x1000)
+    aligned_ws = ctypes.c_void_p(0x100000)
+    # NULL D_out with events, NULL rho, unknown flags, small workspace
+    assert lib.jpet_mlem_denominators(gp, fake, 5, fake, None, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_denominators(gp, fake, 5, None, fake, aligned_ws, 1 << 40, 0, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_denominators(gp, fake, 5, fake, fake, aligned_ws, 1 << 40, 8, None, None) == jpet.JPET_EINVAL
+    assert lib.jpet_mlem_denominators(gp, fake, 5, fake, fake, aligned_ws, 16, 0, None, None) == jpet.JPET_EWORKSPACE
+
+
+def test_plan_candidates_and_named_plans(lib):
+    """Plans that fit come back sorted by the cost model; plan 0 is the first; a named plan is used
+    as named; malformed codes are EINVAL, plans that do not fit the geometry EDOMAIN."""
+    g = jpet.geometry(**GOOD)
+    n = 10_000_000
+    cands = jpet.plan_candidates(g, n)
+    assert len(cands) > 20
+    costs = [c for _, c in cands]
+    assert costs == sorted(costs)
+    assert len({code for code, _ in cands}) == len(cands)
+    assert jpet.launch_info(g, n)["plan"] == cands[0][0]
+    for code, _ in cands[:: max(1, len(cands) // 7)]:
+        info = jpet.launch_info(jpet.with_plan(g, code), n)
+        assert info["plan"] == code and info["binned"] == 1
+        assert info["waves"] == (16 if code & 3 == 2 else 8)
+        assert info["accumulator_bits"] == (32 if code & 4 else 64)
+        assert info["workgroups_per_cu"] == (code >> 3) & 7
+        assert (info["t_bins"] == 1) == ((code >> 6) & 7 == 0)
+        assert info["tile_rows"] == [32, 24, 16, 12, 8][(code >> 9) & 7]
+        assert ws_size(jpet.with_plan(g, code), n)[0] == jpet.JPET_OK
+    # the generic pass can always be named
+    assert jpet.launch_info(jpet.with_plan(g, 3), n)["binned"] == 0
+    # malformed codes
+    for bad in (-1, 4, 1 | (5 << 3), 1 | (1 << 3) | (6 << 6), 1 | (1 << 3) | (5 << 9), 1 | (1 << 3) | (1 << 12), 7):
+        assert ws_size(jpet.with_plan(g, bad), n)[0] == jpet.JPET_EINVAL, bad
+    # well formed but too large for the LDS: 64-bit accumulators, one 32-row tile, no shear,
+    # four workgroups per CU
+    big = 1 | (4 << 3) | (0 << 6) | (0 << 9)
+    assert big not in {c for c, _ in cands}
+    assert ws_size(jpet.with_plan(g, big), n)[0] == jpet.JPET_EDOMAIN
+    # log-likelihood plans: 64-bit accumulators only
+    ll = jpet.plan_candidates(g, n, loglik=True)
+    assert ll and all(code & 4 == 0 for code, _ in ll)
+    b = ctypes.c_size_t(0)
+    acc32 = next(code for code, _ in cands if code & 4)
+    assert lib.jpet_loglik_workspace_size(ctypes.byref(jpet.with_plan(g, acc32)), None, n,
+                                          ctypes.byref(b)) == jpet.JPET_EDOMAIN
+    # rows longer than the register cache: only the generic pass
+    fine = jpet.geometry(**{**GOOD, "sigma_z": 12.0, "pixel": 0.5})
+    assert jpet.plan_candidates(fine, 1000) == [(3, 0.0)]
 
 
 def test_binding_requires_built_library(monkeypatch, tmp_path):

@@ -253,7 +253,7 @@ def test_random_geometries(seed):
     so = oracle.sensitivity(go)
     got, want, st, sto = run_both(g, go, ev, oracle.initial_image(so), n_iter=2)
     assert np.all(np.isfinite(got))
-    for k in ("n_valid", "n_dropped", "n_pairs", "n_zero_denominator"):
+    for k in ("n_valid", "n_dropped", "n_pairs", "n_zero_denominator", "n_kappa_nonpositive"):
         assert st[k] == sto[k], (k, st[k], sto[k])
     if np.linalg.norm(want) > 0:
         assert rel_l2(got, want) <= 1e-4
@@ -587,3 +587,67 @@ def test_loglik_zero_denominator_is_minus_infinity(tiny):
     res = jpet.loglik_grad(g, ev, rho, want_grad_rho=False, want_stats=True)
     assert res.value[0].item() == -math.inf
     assert res.stats["n_zero_denominator"] == res.stats["n_valid"]
+
+
+# ---------------------------------------------------------------------------------------------
+# reading R8: pairs with kappa <= 0 get P := 0 and are counted
+
+
+def _kappa_events(w, pixel, n_y, n_z):
+    """Events of a geometry where kappa changes sign inside ellipses, without the two cases where
+    FP32 against FP64 is not a meaningful comparison: a pixel whose kappa lies within 1e-4 of
+    zero (relative to the event's largest), where the two precisions may take the sign decision
+    differently, and kernel values that spike near kappa = 0+ (more than 30 times the event's
+    median: the Laplace form diverges there).  Events whose every pixel has kappa <= 0 stay."""
+    import sys
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    from laplace import laplace_terms, pixel_centres
+    go = oracle.geometry(**w.geometry())
+    keep = []
+    for e in w.events():
+        p_idx, P = oracle.event_pixels(go, e)
+        if len(P) == 0 or not np.all(np.isfinite(P)):
+            continue
+        y, z = pixel_centres(p_idx, n_y, n_z, pixel)
+        kappa = -2.0 * laplace_terms(w.R, e, y, z, w.sigma_z, w.sigma_dl)[2]
+        if np.any(np.abs(kappa) < 1e-4 * np.abs(kappa).max()):
+            continue
+        pos = P[P > 0]
+        if len(pos) and pos.max() > 30 * np.median(pos):
+            continue
+        keep.append(e)
+    return np.ascontiguousarray(np.array(keep, dtype=np.float32))
+
+
+@pytest.mark.parametrize("pixel,n_y,n_z,binned", [(3.0, 50, 100, 1), (2.0, 70, 120, 0)])
+def test_kappa_nonpositive_pairs_are_zero_and_counted(pixel, n_y, n_z, binned):
+    """Strips 80 mm from the axis, sigma_z = 40 mm against sigma_dl = 6 mm: kappa <= 0 over part of
+    many ellipses and over the whole of some (those events have D = 0).  The binned pass (3 mm
+    pixels) and the generic pass (2 mm: rows too long for the register cache) both count exactly
+    the oracle's pairs with kappa <= 0 and zero-denominator events; two steps within 1e-4."""
+    from jpet_synth import Workload
+    w = Workload("kappa", 80.0, 300.0, 40.0, 6.0, pixel, n_y, n_z, 4000, 2, 77, "random")
+    ev = _kappa_events(w, pixel, n_y, n_z)
+    g, go = geoms(w)
+    assert jpet.launch_info(g, len(ev))["binned"] == binned
+    so = oracle.sensitivity(go)
+    got, want, st, sto = run_both(g, go, ev, oracle.initial_image(so), n_iter=2)
+    print(f"kappa pixel {pixel}: {len(ev)} events, GPU {st}, oracle {sto}", flush=True)
+    assert sto["n_kappa_nonpositive"] > 0 and sto["n_zero_denominator"] > 0
+    for k in ("n_valid", "n_pairs", "n_kappa_nonpositive", "n_zero_denominator"):
+        assert st[k] == sto[k], (k, st[k], sto[k])
+    assert rel_l2(got, want) <= 1e-4
+
+
+def test_loglik_out_of_domain_mask_with_a_caller_workspace_raises(tiny):
+    """A sigma mask out of domain is an error even with a caller-supplied workspace (nothing is
+    written; only a zero denominator after the pass reads as l = -inf)."""
+    w, ev_np, ev = tiny
+    g, _ = geoms(w)
+    s = jpet.sensitivity(g)
+    rho = (s > 0).to(torch.float32)
+    ws = jpet.loglik_workspace(g, ev.shape[0])
+    with pytest.raises(jpet.JpetError):
+        jpet.loglik_grad(g, ev, rho, s=s, ws=ws, sigma_mask=(0.0, 63.0))
+    with pytest.raises(jpet.JpetError):
+        jpet.loglik_grad(g, ev, rho, s=s, ws=ws, sigma_mask=(0.0, 63.0), want_stats=True)

@@ -580,3 +580,45 @@ def test_position_dependent_mlem_conserves_counts():
     # the log-likelihood is defined for a constant sigma_z only
     with pytest.raises(ValueError):
         oracle.loglik_grad(g, ev, rho, s=s)
+
+
+# --------------------------------------------------------------------------------------------
+# Reading R8: kappa <= 0 (the angular Gaussian integral behind Eq. 7 diverges)
+
+
+def test_kappa_nonpositive_pixels_get_zero_and_are_counted():
+    """A geometry where kappa changes sign inside the 3-sigma ellipse (strips 80 mm from the axis,
+    sigma_z = 40 mm against sigma_dl = 6 mm).  With kappa = -2 g2 computed from the measurement
+    model's own Taylor coefficients, the oracle's kernel is 0 at exactly the in-ellipse pixels with
+    kappa <= 0, is the Laplace form elsewhere, and the oracle counts exactly those pairs."""
+    from jpet_synth import Workload
+    from laplace import laplace_terms, pixel_centres
+    Rk, Lk, sz, sdl, pix, ny, nz = 80.0, 300.0, 40.0, 6.0, 3.0, 50, 100
+    w = Workload("kappa", Rk, Lk, sz, sdl, pix, ny, nz, 200, 1, 77, "random")
+    ev = w.events()
+    for variant in (0, 1):
+        g = oracle.geometry(**w.geometry(kernel_variant=variant))
+        count, total, checked = 0, 0, 0
+        for e in ev:
+            p_idx, P = oracle.event_pixels(g, e)
+            if len(p_idx) == 0:
+                continue
+            y, z = pixel_centres(p_idx, ny, nz, pix)
+            g0, g1, g2 = laplace_terms(Rk, e, y, z, sz, sdl, variant)
+            kappa = -2.0 * g2
+            sure = np.abs(kappa) > 1e-7 * np.abs(kappa).max()
+            assert np.array_equal((P == 0)[sure], (kappa <= 0)[sure])
+            count += int((kappa <= 0).sum())
+            total += len(P)
+            # values where the exponent is moderate (near kappa = 0+ it grows without bound and
+            # the Taylor coefficients' own rounding is amplified by it)
+            ok = sure & (kappa > 0)
+            expo = g0[ok] - g1[ok] ** 2 / (4 * g2[ok])
+            mod = (np.abs(expo) <= 50.0) & (kappa[ok] > 1e-2 * kappa.max())
+            want = np.sqrt(np.pi / -g2[ok][mod]) * np.exp(expo[mod])
+            want *= math.sqrt(1 / sz ** 4 / sdl ** 2) / (2 * math.pi) ** 1.5
+            np.testing.assert_allclose(P[ok][mod], want, rtol=1e-7)
+            checked += int(mod.sum())
+        _, st = oracle.mlem(g, ev, np.ones((ny, nz)), 1)
+        assert 0 < count < total and checked > 0.5 * total
+        assert st["n_kappa_nonpositive"] == count
