@@ -156,13 +156,30 @@ int do_prepare(const Geo& geo, const Plan& p, const float* events, int64_t n, co
 // LDS row-pitch alignment of the binned pass's column-major region
 static const int kBankAlign = 64;
 
+// Events per batch: as many as the rows of the largest ellipses allow on the workgroup's threads.
+static int events_per_batch(int waves, int rows_max) {
+  const int epb = (64 * waves) / rows_max;
+  return epb < 32 ? epb : 32;
+}
+
+// Dynamic LDS of the tiled pass for a region of RY x W pixels (row pitch `pitch`): the image and the
+// accumulators, the double buffer of per-event constants, the per-row column shifts.
+static size_t tiled_lds_layout(int pitch, int W, int RY, int acc32, int epb, bool loglik, int* ev_at, int* off_at) {
+  const size_t region = (size_t)pitch * (size_t)W * (acc32 ? 8u : 12u);
+  const size_t ev = align_up(region, 16);
+  const size_t off = ev + 2u * (size_t)epb * (size_t)event_const_bytes(loglik);
+  if (ev_at) *ev_at = (int)ev;
+  if (off_at) *off_at = (int)off;
+  return align_up(off + 4u * (size_t)RY, 16);
+}
+
 // Derived fields of a binned plan whose region (waves, acc32, tile, halo, t bins) is set.
 static void finish_plan(const jpet_geometry* g, int rows_max, int64_t n, Plan& p) {
   const double pix = g->pixel;
-  const int epb = (64 * p.waves) / rows_max;
-  p.ev_per_batch = epb < 32 ? epb : 32;
-  p.batch_bytes =
-      (int)((p.ev_per_batch * sizeof(EvConst) + 4u * (64u + kBlockTailWords) * (unsigned)p.waves + 255u) / 256u * 256u);
+  p.ev_per_batch = events_per_batch(p.waves, rows_max);
+  p.cbytes = p.ev_per_batch * event_const_bytes(p.loglik != 0);
+  p.lds_bytes = tiled_lds_layout(p.pitch, p.W, p.RY, p.acc32, p.ev_per_batch, p.loglik != 0, &p.lds_ev, &p.lds_off);
+  p.batch_bytes = (int)(((unsigned)p.cbytes + 4u * (64u + kBlockTailWords) * (unsigned)p.waves + 255u) / 256u * 256u);
   p.nty = (g->n_y + p.TY - 1) / p.TY;
   // sheared column span: the widest over the t bins
   int span = g->n_z;
@@ -246,11 +263,11 @@ void plan_candidates(const jpet_geometry* g, double msz, double mdl, int64_t n, 
   // plus, at most, one partial item per bin.
   // (the log-likelihood pass, with its derivative terms, keeps 5 / 4 / 4 / 4)
   const int simd_waves = loglik ? (maxlen <= 16 ? 5 : 4) : maxlen <= 16 ? 8 : maxlen <= 32 ? 6 : maxlen <= 48 ? 5 : 4;
-  // LDS per CU, the passes' static LDS (batch buffers; more in the log-likelihood pass), and the
-  // allocation granule: measured on gfx950, three workgroups of 51,984 bytes each run on one CU
-  // but three of 54,032 bytes do not (the pass then runs 27% slower), so a workgroup's LDS is
-  // counted in whole 2 KB granules.
-  const size_t kLdsPerCU = 160 * 1024, kStatic = loglik ? 8 * 1024 : 7 * 1024, kGranule = 2048;
+  // LDS per CU, the passes' static LDS (per-event denominators; the log-likelihood pass also its
+  // derivative sums), and the allocation granule: measured on gfx950, three workgroups of 51,984
+  // bytes each run on one CU but three of 54,032 bytes do not (the pass then runs 27% slower), so
+  // a workgroup's LDS is counted in whole 2 KB granules.
+  const size_t kLdsPerCU = 160 * 1024, kStatic = loglik ? 2 * 1024 : 1024, kGranule = 2048;
   const double pairs_per_event = 3.14159265358979323846 * hy_px * (3.0 * msz / sqrt(2.0) / pix);
   const double nn = (double)(n > 0 ? n : 1);
   for (int waves : {8, 16}) {
@@ -275,7 +292,8 @@ void plan_candidates(const jpet_geometry* g, double msz, double mdl, int64_t n, 
             // in the accumulator array (W columns of 4 or 8 bytes)
             const int RY = T + 2 * HY, W = T + 2 * HZ;
             const int pitch = (RY + kBankAlign - 1) / kBankAlign * kBankAlign;
-            const size_t bytes = (size_t)pitch * (size_t)W * (acc32 ? 8u : 12u);
+            const size_t bytes =
+                tiled_lds_layout(pitch, W, RY, acc32, events_per_batch(waves, rows_max), loglik, nullptr, nullptr);
             const int reach = acc32 ? W : 2 * W;
             // thread words address columns with 8 bits and rows with 9 bits
             if (bytes > budget || reach < maxlen || W > 256 || RY > 512) continue;
@@ -290,8 +308,8 @@ void plan_candidates(const jpet_geometry* g, double msz, double mdl, int64_t n, 
             p.HZ = HZ;
             p.RY = RY;
             p.W = W;
-            p.lds_bytes = bytes;
             p.wgs = wgs;
+            p.loglik = loglik ? 1 : 0;
             p.code = plan_code(waves, acc32, wgs, dti, ti);
             if (dt != 0.0) {
               p.ntb = (int)ceil(2.0 * tmax / dt);

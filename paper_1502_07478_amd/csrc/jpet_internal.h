@@ -60,14 +60,39 @@ struct EvConst {
 
 static_assert(sizeof(EvConst) == 64, "EvConst is copied to LDS in 16-byte units");
 
+// Per-event constants of the binned MLEM pass (80 bytes): every row constant of the kernel along
+// a pixel row as a polynomial in r, the row's index in its bin's region (Eq. 7-12, with Y the row's
+// y, dy = Y - y~ and b1 = z - z~ - dy tan, all linear in r):
+//   b1 at the row's first pixel = pix c + BT r + B0                (c: the pixel's region column)
+//   kappa  = KR(r) + KB(r) b1,      KR = K0 + K1 r + K2 r^2,  KB = KB0 + KB1 r
+//   sqrt(S) gamma^ = GR(r) + GB(r) b1,  GR = S0 + S1 r + S2 r^2,  GB = GB0 + GB1 r
+//   S q    = s2u b1^2 + Q(r),       Q = Q0 + Q1 r + Q2 r^2
+// so that along the row, at its j-th pixel, kappa = kappa_0 + j KB pix, sqrt(S) gamma^ =
+// gs_0 + j GB pix and S q = qa j^2 + QB b1 j + S q_0 (qa = s2u pix^2, QB = 2 s2u pix).  The
+// coefficients are formed in double precision at prepare time and rounded once.
+struct EvRow {
+  float B0, BT;
+  float K0, K1, K2, KB0, KB1;
+  float S0, S1, S2, GB0, GB1;
+  float Q0, Q1, Q2;
+  float qa, QB, s2u;
+  int32_t index;  // position of the event in the caller's array
+  int32_t pad;
+};
+
+static_assert(sizeof(EvRow) == 80, "EvRow is copied to LDS in 16-byte units");
+
 // Thread word of the binned pass: the pixel row a thread owns in a batch, relative to its bin's
 // region: bits 0-7 first column (sheared, region-local), 8-16 row (region-local), 17-23 pixel
 // count (0: idle thread), 24-28 event within the batch.
 constexpr uint32_t kWordCol = 0, kWordRow = 8, kWordLen = 17, kWordEv = 24;
 
-// A batch block: ev_per_batch EvConst, then one thread word per thread of the workgroup, then for
-// each wavefront its longest row and its shortest non-empty row (pixels).
+// A batch block: ev_per_batch per-event constants (EvRow for the MLEM pass, EvConst for the
+// log-likelihood pass), then one thread word per thread of the workgroup, then for each wavefront
+// its longest row (pixels; bit kGuardBit set when a row of the wavefront may reach kappa <= 0 and
+// needs the per-pixel test) and its shortest non-empty row.
 constexpr int kBlockTailWords = 2;
+constexpr uint32_t kGuardBit = 31;
 
 // Spatial binning of events and launch shape of the tiled event pass.
 //
@@ -99,7 +124,16 @@ struct Plan {
   int wgs;              // workgroups resident per CU the region was sized for
   int32_t code;         // plan code (see plan_code_* below): what jpet_geometry.plan names
   int invalid;          // 1: the requested code does not fit this geometry (JPET_EDOMAIN)
+  int loglik;           // 1: a plan of the log-likelihood pass (EvConst blocks, 64-bit slots)
+  int cbytes;           // per-event constants of one batch (bytes)
+  // dynamic LDS of the tiled pass: the region's image and accumulators from 0, then at lds_ev
+  // two buffers of cbytes (the current and the next batch's constants), then at lds_off one
+  // int per region row (its sheared column shift)
+  int lds_ev, lds_off;
 };
+
+// Bytes of the per-event constants of one event in a batch block.
+inline int event_const_bytes(bool loglik) { return loglik ? (int)sizeof(EvConst) : (int)sizeof(EvRow); }
 
 // Plan codes, the value of jpet_geometry.plan that names one plan: 0 lets the cost model choose;
 // otherwise bits 0-1 are the kind (1: binned pass with 8-wavefront workgroups, 2: with 16, 3: the

@@ -21,13 +21,12 @@ namespace jpet {
 namespace {
 
 constexpr int kMaxBatch = 32;  // events per batch (the plan keeps ev_per_batch <= 32)
-constexpr int kMaxRows = 512;  // region rows (the plan keeps RY <= 512)
 constexpr int kChunk = 4;      // pixels evaluated per branch-free step
 
+// Static LDS of the pass; the per-event constants (double buffer: the next batch is copied in
+// while this one runs) and the per-row column shifts sit in the dynamic LDS after the region.
 struct PassShared {
-  EvConst ev[2][kMaxBatch];  // double buffer: the next batch is copied in while this one runs
   double D[3][kMaxBatch];    // batch b's denominators in D[b % 3]: filled, read, cleared in turn
-  int off[kMaxRows];         // sheared column shift of each region row
   unsigned zero, bad;
 };
 
@@ -222,12 +221,12 @@ __device__ __forceinline__ void pass2g(const float (&m)[MAXLEN], float invD, int
 // Copies a batch's per-event constants into LDS with direct global-to-LDS loads issued by the
 // first wavefront (16 bytes per lane, 1 KB per instruction); completion is awaited before the
 // next workgroup barrier.
-__device__ __forceinline__ void copy_consts(const unsigned char* __restrict__ src, EvConst* dst, int bytes, int tid) {
+__device__ __forceinline__ void copy_consts(const unsigned char* __restrict__ src, unsigned char* dst, int bytes,
+                                            int tid) {
   if (tid < WAVE) {
     for (int off = 0; off < bytes; off += WAVE * 16) {
       if (off + tid * 16 < bytes)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint4*>(src + off + tid * 16),
-                                         reinterpret_cast<unsigned char*>(dst) + off, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint4*>(src + off + tid * 16), dst + off, 16, 0, 0);
     }
   }
 }
@@ -283,16 +282,19 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   const float rs = 0.84932180028801904272f;  // sqrt(log2(e) / 2)
   const float faf = (float)g.fa;
   const int nbatch = (it.count + p.ev_per_batch - 1) / p.ev_per_batch;
-  const int cbytes = p.ev_per_batch * (int)sizeof(EvConst);
+  const int cbytes = p.cbytes;
   const unsigned char* blk0 = blocks + (size_t)it.batch * (size_t)p.batch_bytes;
+  unsigned char* const ev_lds = smem + p.lds_ev;  // two buffers of cbytes
+  int* const off_s = reinterpret_cast<int*>(smem + p.lds_off);
 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wl_off = cbytes + 4 * 64 * WAVES + 4 * wave;  // this wavefront's longest row
   const int wn_off = wl_off + 4 * WAVES;                   // and its shortest non-empty row
-  // first batch: constants to LDS, this thread's word and its wavefront's row lengths
-  copy_consts(blk0, ps.ev[0], cbytes, tid);
+  // first batch: constants to LDS, this thread's word and its wavefront's row lengths (and whether
+  // a row of the wavefront needs the per-pixel kappa test)
+  copy_consts(blk0, ev_lds, cbytes, tid);
   uint32_t word = reinterpret_cast<const uint32_t*>(blk0 + cbytes)[tid];
-  int wl = *reinterpret_cast<const int*>(blk0 + wl_off);
+  uint32_t wlw = *reinterpret_cast<const uint32_t*>(blk0 + wl_off);
   int wn = *reinterpret_cast<const int*>(blk0 + wn_off);
   if (tid < kMaxBatch) {
     ps.D[0][tid] = 0.0;
@@ -319,7 +321,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   }
   // stage the region of the current image (column-major), clear the accumulators: wavefronts take
   // columns, lanes take rows
-  for (int r = tid; r < p.RY; r += blockDim.x) ps.off[r] = shear_offset(g, tc, rbase + r);
+  for (int r = tid; r < p.RY; r += blockDim.x) off_s[r] = shear_offset(g, tc, rbase + r);
   __syncthreads();
   for (int cl = wave; cl < p.W; cl += WAVES) {
     const int kc = kbase + cl;
@@ -328,7 +330,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       const int r = rbase + rl;
       float v = 0.0f;
       if (rl < p.RY && r >= 0 && r < g.n_y) {
-        const int k = kc + ps.off[rl];
+        const int k = kc + off_s[rl];
         if (k >= 0 && k < g.n_z) v = rho[(int64_t)r * g.n_z + k];
       }
       rho_s[q] = v;
@@ -385,14 +387,17 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
     if (bi < nbatch) {
       const int buf = bi & 1;
       const int nb = min(p.ev_per_batch, it.count - bi * p.ev_per_batch);
+      const unsigned char* evb = ev_lds + buf * cbytes;  // this batch's constants
+      const int wl = (int)(wlw & 0x7fffffffu);
+      const bool guard = (wlw >> kGuardBit) != 0u;  // wavefront-uniform
       // prefetch the next batch: constants into the other LDS buffer, this thread's next word
-      uint32_t next = 0u;
-      int wl_next = 0, wn_next = 0;
+      uint32_t next = 0u, wlw_next = 0u;
+      int wn_next = 0;
       if (bi + 1 < nbatch) {
         const unsigned char* blk = blk0 + (size_t)(bi + 1) * (size_t)p.batch_bytes;
-        copy_consts(blk, ps.ev[buf ^ 1], cbytes, tid);
+        copy_consts(blk, ev_lds + (buf ^ 1) * cbytes, cbytes, tid);
         next = reinterpret_cast<const uint32_t*>(blk + cbytes)[tid];
-        wl_next = *reinterpret_cast<const int*>(blk + wl_off);
+        wlw_next = *reinterpret_cast<const uint32_t*>(blk + wl_off);
         wn_next = *reinterpret_cast<const int*>(blk + wn_off);
       }
 
@@ -400,31 +405,30 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       const int len = (int)((word >> kWordLen) & 127u);
       const int e = (int)((word >> kWordEv) & 31u);
       int base = 0;
-      bool safe = true;
       RowF rk = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 1e30f};  // idle lane: every kernel value is 0
       RowD rd = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       if (len > 0) {
         const int kl = (int)((word >> kWordCol) & 255u);
         const int rl = (int)((word >> kWordRow) & 511u);
-        const EvConst& c = ps.ev[buf][e];
-        // region-relative coordinates: the row's y, y - y~, and z of its first pixel - z~ - t (y - y~)
         const float rlf = (float)rl;
-        const float Y = fmaf(rlf, pixf, Yb);
-        const float dy = fmaf(rlf, pixf, -c.yr);
-        const float b10 = fmaf((float)(kl + ps.off[rl]), pixf, -fmaf(c.t, dy, c.zr));
-        const float kr = fmaf(c.GK, fmaf(faf, Y, 2.0f * dy), fmaf(c.A1, R2 + Y * Y, Y * fmaf(c.A2, Y, c.A3 * dy)));
-        const float kb = c.KB * Y;
-        const float gb = c.GB * Y;
-        rk.kap0 = fmaf(kb, b10, kr);
-        rk.dkap = kb * pixf;
-        rk.gs0 = rs * fmaf(gb, b10, fmaf(c.GG, dy, c.G1 * Y * dy));
-        rk.dgs = rs * gb * pixf;
-        // S 2u of this event (its own sigma_z); the log-likelihood mode has one sigma_z for all
-        const float s2u = GRAD ? S2u : c.S2u;
-        rk.qa = s2u * pixf * pixf;
-        rk.qb = 2.0f * s2u * b10 * pixf;
-        rk.qc = fmaf(s2u * b10, b10, c.Q3s * dy * dy);
         if constexpr (GRAD) {
+          const EvConst& c = reinterpret_cast<const EvConst*>(evb)[e];
+          // region-relative coordinates: the row's y, y - y~, and z of its first pixel - z~ - t (y - y~)
+          const float Y = fmaf(rlf, pixf, Yb);
+          const float dy = fmaf(rlf, pixf, -c.yr);
+          const float b10 = fmaf((float)(kl + off_s[rl]), pixf, -fmaf(c.t, dy, c.zr));
+          const float kr =
+              fmaf(c.GK, fmaf(faf, Y, 2.0f * dy), fmaf(c.A1, R2 + Y * Y, Y * fmaf(c.A2, Y, c.A3 * dy)));
+          const float kb = c.KB * Y;
+          const float gb = c.GB * Y;
+          rk.kap0 = fmaf(kb, b10, kr);
+          rk.dkap = kb * pixf;
+          rk.gs0 = rs * fmaf(gb, b10, fmaf(c.GG, dy, c.G1 * Y * dy));
+          rk.dgs = rs * gb * pixf;
+          // the log-likelihood mode has one sigma_z for all events
+          rk.qa = S2u * pixf * pixf;
+          rk.qb = 2.0f * S2u * b10 * pixf;
+          rk.qc = fmaf(S2u * b10, b10, c.Q3s * dy * dy);
           rd.b10 = b10;
           rd.Kzh0 = 0.5f * iu * fmaf(kb, b10, c.A1 * (R2 + Y * Y));
           rd.dKzh = 0.5f * iu * kb * pixf;
@@ -433,23 +437,35 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
           rd.Gl = iw * c.G1 * Y * dy;
           rd.Klh = 0.5f * iw * Y * fmaf(c.A2, Y, c.A3 * dy);
           rd.cw = cwf - 0.5f * iS * iw * c.Q3s * dy * dy;
+        } else {
+          // the row constants from the event's polynomials in the region row (see EvRow)
+          const EvRow& c = reinterpret_cast<const EvRow*>(evb)[e];
+          const float b10 = fmaf(pixf, (float)(kl + off_s[rl]), fmaf(c.BT, rlf, c.B0));
+          const float kb = fmaf(c.KB1, rlf, c.KB0);
+          const float gb = fmaf(c.GB1, rlf, c.GB0);
+          rk.kap0 = fmaf(kb, b10, fmaf(fmaf(c.K2, rlf, c.K1), rlf, c.K0));
+          rk.dkap = kb * pixf;
+          rk.gs0 = fmaf(gb, b10, fmaf(fmaf(c.S2, rlf, c.S1), rlf, c.S0));
+          rk.dgs = gb * pixf;
+          rk.qa = c.qa;
+          rk.qb = c.QB * b10;
+          rk.qc = fmaf(c.s2u * b10, b10, fmaf(fmaf(c.Q2, rlf, c.Q1), rlf, c.Q0));
         }
-        const float kend = fmaf((float)(len - 1), rk.dkap, rk.kap0);
-        safe = rk.kap0 > 1e-3f * fabsf(rk.kap0) && kend > 1e-3f * fabsf(rk.kap0);
         base = kl * pitch + rl;
       }
 
-      // pass 1: m = P rho along the row (log-likelihood mode: m = P), D partial sums
+      // pass 1: m = P rho along the row (log-likelihood mode: m = P), D partial sums; the per-pixel
+      // kappa test only in wavefronts whose rows may need it (decided at prepare time)
       int nbad = 0;  // pixels of this thread's row with kappa <= 0 (P := 0)
       float D, Du = 0.0f, Dw = 0.0f;
       if constexpr (GRAD) {
-        if (__any(!safe)) {
+        if (guard) {
           pass1g<MAXLEN, true>(rk, rd, qa, pixf, cuf, irs, rho_s, base, pitch, len, wn, wl, m, &nbad, D, Du, Dw);
         } else {
           pass1g<MAXLEN, false>(rk, rd, qa, pixf, cuf, irs, rho_s, base, pitch, len, wn, wl, m, &nbad, D, Du, Dw);
         }
       } else {
-        if (__any(!safe)) {
+        if (guard) {
           D = pass1<MAXLEN, true>(rk, rk.qa, rho_s, base, pitch, len, wn, wl, m, &nbad);
         } else {
           D = pass1<MAXLEN, false>(rk, rk.qa, rho_s, base, pitch, len, wn, wl, m, &nbad);
@@ -457,24 +473,30 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       }
       if (nbad) atomicAdd(&ps.bad, (unsigned)nbad);
 
-      // per-event denominators: segmented reduction over the wavefront's rows
+      // per-event denominators
       double* Dc = ps.D[bi % 3];
-      unsigned long long act = __ballot(len > 0);
-      while (act) {
-        const int leader = __ffsll((long long)act) - 1;
-        const int el = __builtin_amdgcn_readlane(e, leader);
-        const bool mine = len > 0 && e == el;
-        const float v = wave_sum_dpp(mine ? D : 0.0f);
-        if (lane == 0) atomicAdd(&Dc[el], (double)v);
-        if constexpr (GRAD) {
+      if constexpr (GRAD) {
+        // segmented reduction over the wavefront's rows, one event at a time
+        unsigned long long act = __ballot(len > 0);
+        while (act) {
+          const int leader = __ffsll((long long)act) - 1;
+          const int el = __builtin_amdgcn_readlane(e, leader);
+          const bool mine = len > 0 && e == el;
+          const float v = wave_sum_dpp(mine ? D : 0.0f);
+          if (lane == 0) atomicAdd(&Dc[el], (double)v);
           const float vu = wave_sum_dpp(mine ? Du : 0.0f);
           const float vw = wave_sum_dpp(mine ? Dw : 0.0f);
           if (lane == 0) {
             atomicAdd(&gsh->Du[bi % 3][el], vu);
             atomicAdd(&gsh->Dw[bi % 3][el], vw);
           }
+          act &= ~__ballot(mine);
         }
-        act &= ~__ballot(mine);
+      } else {
+        // every row adds its partial sum in double precision: the LDS atomic unit does the
+        // reduction (no VALU work beyond the conversion), and FP64 sums of FP32 partials do not
+        // depend on the order of the additions to FP32 precision
+        if (len > 0) unsafeAtomicAdd(&Dc[e], (double)D);
       }
       // batch bi + 1 accumulates into D[(bi + 1) % 3], last read (as batch bi - 2's) before the
       // previous barrier
@@ -485,14 +507,14 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
           gsh->Dw[(bi + 1) % 3][tid] = 0.0f;
         }
       }
-      if constexpr (GRAD) pidx = tid < nb ? ps.ev[buf][tid].index : -1;
+      if constexpr (GRAD) pidx = tid < nb ? reinterpret_cast<const EvConst*>(evb)[tid].index : -1;
       plen = len;
       pbase = base;
       pe = e;
       pwl = wl;
       pwn = wn;
       word = next;
-      wl = wl_next;
+      wlw = wlw_next;
       wn = wn_next;
     }
     __builtin_amdgcn_s_waitcnt(0);
@@ -506,7 +528,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       const unsigned long long a = (unsigned long long)acc_s[cl * pitch + rl] << flush_shift;
       if (a == 0ull) continue;
       const int r = rbase + rl;
-      const int k = kc + ps.off[rl];
+      const int k = kc + off_s[rl];
       if (r >= 0 && r < g.n_y && k >= 0 && k < g.n_z) {
         if constexpr (GRAD) {
           unsafeAtomicAdd(reinterpret_cast<double*>(acc) + (int64_t)r * g.n_z + k, __longlong_as_double((long long)a));

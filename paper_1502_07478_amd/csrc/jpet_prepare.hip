@@ -196,6 +196,51 @@ __global__ void __launch_bounds__(256) k_items(int nbins, int ev_per_wg, int ev_
   }
 }
 
+// The per-event constants of the binned MLEM pass (EvRow) for a bin whose region starts at pixel
+// row rbase and (sheared) column kbase, in double precision.  With r the region row, the row's
+// y is Y = Yb + pix r and dy = Y - y~ = pix r - yr, both linear in r; each row constant of the
+// kernel (Eq. 7-12; see EvRow) is then a polynomial of degree <= 2 in r, expanded here.
+__device__ EvRow event_row_constants(const Geo& g, const EventRec& e, int rbase, int kbase) {
+  const double pix = g.pixel, t = e.t, c = e.c, c2 = c * c, f = g.fa;
+  const double u = g.u * e.su, w = g.w;  // u: this event's sigma_z^-2
+  const double Yb = g.y0 + (double)rbase * pix;
+  const double yr = e.y - Yb;                          // dy = pix r - yr
+  const double zr = e.z - (g.z0 + (double)kbase * pix);
+  const double rs = 0.84932180028801904272;            // sqrt(log2(e) / 2)
+  const double S = kHalfLog2e;
+  // kappa without its b1 term: A1 (R^2 + Y^2) + A2 Y^2 + A3 Y dy + GK (fa Y + 2 dy)
+  const double A1 = 2.0 * u * c2 * c2, A2 = w * f * f * c2 * t * t, A3 = 4.0 * w * c2 * (1.0 + 2.0 * t * t);
+  const double GK = -4.0 * g.gamma * g.R * c2 * c * t;
+  const double KB = -4.0 * u * t * c2;                 // kappa's slope in b1 per unit Y
+  // sqrt(S) gamma^ without its b1 term: rs (G1 Y dy + GG dy); its slope in b1 per unit Y: rs GB
+  const double G1 = 2.0 * f * w * c2 * t, GG = -4.0 * g.gamma * g.R * c2 * c, GB = -2.0 * u * c2;
+  const double Q3 = S * 4.0 * w * c2;                  // S q = S 2u b1^2 + Q3 dy^2
+  EvRow k;
+  k.B0 = (float)(t * yr - zr);
+  k.BT = (float)(-t * pix);
+  // Y^2 = Yb^2 + 2 Yb pix r + pix^2 r^2,  Y dy = -Yb yr + (Yb - yr) pix r + pix^2 r^2
+  k.K0 = (float)(A1 * g.R * g.R + (A1 + A2) * Yb * Yb - A3 * Yb * yr + GK * (f * Yb - 2.0 * yr));
+  k.K1 = (float)(((A1 + A2) * 2.0 * Yb + A3 * (Yb - yr) + GK * (f + 2.0)) * pix);
+  k.K2 = (float)((A1 + A2 + A3) * pix * pix);
+  k.KB0 = (float)(KB * Yb);
+  k.KB1 = (float)(KB * pix);
+  k.S0 = (float)(rs * (-G1 * Yb * yr - GG * yr));
+  k.S1 = (float)(rs * (G1 * (Yb - yr) + GG) * pix);
+  k.S2 = (float)(rs * G1 * pix * pix);
+  k.GB0 = (float)(rs * GB * Yb);
+  k.GB1 = (float)(rs * GB * pix);
+  k.Q0 = (float)(Q3 * yr * yr);
+  k.Q1 = (float)(-2.0 * Q3 * yr * pix);
+  k.Q2 = (float)(Q3 * pix * pix);
+  const double s2u = S * 2.0 * u;
+  k.qa = (float)(s2u * pix * pix);
+  k.QB = (float)(2.0 * s2u * pix);
+  k.s2u = (float)s2u;
+  k.index = e.index;
+  k.pad = 0;
+  return k;
+}
+
 // Batch blocks of the binned pass: one workgroup per item builds, for each batch of ev_per_batch
 // events, the per-event constants and the thread words.  Rows are given to threads so that a
 // wavefront holds rows of nearly equal length: each event's rows are cut into rings of 32 rows
@@ -233,8 +278,7 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
   for (int e0 = 0, bi = 0; e0 < it.count; e0 += p.ev_per_batch, ++bi) {
     const int nb = min(p.ev_per_batch, it.count - e0);
     unsigned char* blk = blocks + (size_t)(it.batch + bi) * (size_t)p.batch_bytes;
-    EvConst* evc = reinterpret_cast<EvConst*>(blk);
-    uint32_t* words = reinterpret_cast<uint32_t*>(blk + (size_t)p.ev_per_batch * sizeof(EvConst));
+    uint32_t* words = reinterpret_cast<uint32_t*>(blk + p.cbytes);
     __syncthreads();
     if (tid < nb) {
       const EventRec e = evs[it.start + e0 + tid];
@@ -244,28 +288,32 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
       const int K = min(mrow, nrows - mrow) >> 4;
       K_s[tid] = K;
       top_s[tid] = mrow - 16 * K;
-      const float t = (float)e.t, c2 = (float)(e.c * e.c), u = (float)(g.u * e.su), w = (float)g.w,
-                  fa = (float)g.fa;
-      EvConst k;
-      k.yr = (float)(e.y - (g.y0 + (double)rbase * g.pixel));
-      k.zr = (float)(e.z - (g.z0 + (double)kbase * g.pixel));
-      k.index = e.index;
-      k.S2u = (float)(kHalfLog2e * 2.0 * (g.u * e.su));
-      k.t = t;
-      k.A1 = 2.0f * u * c2 * c2;
-      k.A2 = w * fa * fa * c2 * t * t;
-      k.A3 = 4.0f * w * c2 * (1.0f + 2.0f * t * t);
-      k.KB = -4.0f * u * t * c2;
-      k.G1 = 2.0f * fa * w * c2 * t;
-      k.GB = -2.0f * u * c2;
-      k.Q3s = (float)kHalfLog2e * 4.0f * w * c2;
-      {
-        const double c3 = e.c * e.c * e.c;
-        k.GK = (float)(-4.0 * g.gamma * g.R * c3 * e.t);
-        k.GG = (float)(-4.0 * g.gamma * g.R * c3);
+      if (p.loglik) {
+        const float t = (float)e.t, c2 = (float)(e.c * e.c), u = (float)(g.u * e.su), w = (float)g.w,
+                    fa = (float)g.fa;
+        EvConst k;
+        k.yr = (float)(e.y - (g.y0 + (double)rbase * g.pixel));
+        k.zr = (float)(e.z - (g.z0 + (double)kbase * g.pixel));
+        k.index = e.index;
+        k.S2u = (float)(kHalfLog2e * 2.0 * (g.u * e.su));
+        k.t = t;
+        k.A1 = 2.0f * u * c2 * c2;
+        k.A2 = w * fa * fa * c2 * t * t;
+        k.A3 = 4.0f * w * c2 * (1.0f + 2.0f * t * t);
+        k.KB = -4.0f * u * t * c2;
+        k.G1 = 2.0f * fa * w * c2 * t;
+        k.GB = -2.0f * u * c2;
+        k.Q3s = (float)kHalfLog2e * 4.0f * w * c2;
+        {
+          const double c3 = e.c * e.c * e.c;
+          k.GK = (float)(-4.0 * g.gamma * g.R * c3 * e.t);
+          k.GG = (float)(-4.0 * g.gamma * g.R * c3);
+        }
+        k.pad[0] = k.pad[1] = 0;
+        reinterpret_cast<EvConst*>(blk)[tid] = k;
+      } else {
+        reinterpret_cast<EvRow*>(blk)[tid] = event_row_constants(g, e, rbase, kbase);
       }
-      k.pad[0] = k.pad[1] = 0;
-      evc[tid] = k;
     }
     __syncthreads();
     if (tid < WAVE) {  // ring slots (ring-major, then event) and the tip prefix
@@ -314,6 +362,7 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
       ri = qq < top ? qq : ((ev_s[e].r1 - ev_s[e].r0 + 1) >> 1) + 16 * K_s[e] + (qq - top);
     }
     uint32_t word = 0u;
+    bool guard = false;  // this row may reach kappa <= 0: the pass tests every pixel
     if (e >= 0) {
       const EventRec ev = ev_s[e];
       const int i = ev.r0 + ri;
@@ -327,6 +376,12 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
         } else {
           word = ((uint32_t)kl << kWordCol) | ((uint32_t)rl << kWordRow) | ((uint32_t)n << kWordLen) |
                  ((uint32_t)e << kWordEv);
+          // kappa is affine along the row: its smallest value is at one of the two ends; rows
+          // whose ends both keep a margin of 1e-3 of the first value can skip the test
+          double kf, ks;
+          (void)row_constants(g, ev, i, klo, &kf, &ks);
+          const double kend = kf + (double)(n - 1) * ks;
+          guard = !(kf > 1e-3 * fabs(kf) && kend > 1e-3 * fabs(kf));
         }
       }
     }
@@ -335,8 +390,9 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
       const int len = (int)((word >> kWordLen) & 127u);
       const int wl = wave_max_i(len);
       const int wmin = -wave_max_i(len > 0 ? -len : -wl);  // shortest non-empty row (0: none)
+      const bool wguard = __any(guard);
       if (lane == 0) {
-        words[64 * p.waves + (tid >> 6)] = (uint32_t)wl;
+        words[64 * p.waves + (tid >> 6)] = (uint32_t)wl | (wguard ? 1u << kGuardBit : 0u);
         words[65 * p.waves + (tid >> 6)] = (uint32_t)wmin;
       }
     }
