@@ -284,7 +284,8 @@ typedef struct jpet_launch_info {
   int32_t workgroups_per_cu; /* resident workgroups per CU the LDS region is sized for (0: generic) */
   int32_t accumulator_shift; /* 32-bit accumulators: units of 2^-accumulator_shift counts; 0 for 64-bit
                                 ones (2^-32 units) */
-  int32_t pad;
+  int32_t row_segments;  /* 1: a thread holds a whole ellipse row; 2: rows longer than row_cache
+                            pixels are split in two, one thread each */
 } jpet_launch_info;
 
 int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_info* info);

@@ -156,9 +156,10 @@ int do_prepare(const Geo& geo, const Plan& p, const float* events, int64_t n, co
 // LDS row-pitch alignment of the binned pass's column-major region
 static const int kBankAlign = 64;
 
-// Events per batch: as many as the rows of the largest ellipses allow on the workgroup's threads.
-static int events_per_batch(int waves, int rows_max) {
-  const int epb = (64 * waves) / rows_max;
+// Events per batch: as many as the row segments of the largest ellipses allow on the workgroup's
+// threads.
+static int events_per_batch(int waves, int units_max) {
+  const int epb = (64 * waves) / units_max;
   return epb < 32 ? epb : 32;
 }
 
@@ -176,7 +177,7 @@ static size_t tiled_lds_layout(int pitch, int W, int RY, int acc32, int epb, boo
 // Derived fields of a binned plan whose region (waves, acc32, tile, halo, t bins) is set.
 static void finish_plan(const jpet_geometry* g, int rows_max, int64_t n, Plan& p) {
   const double pix = g->pixel;
-  p.ev_per_batch = events_per_batch(p.waves, rows_max);
+  p.ev_per_batch = events_per_batch(p.waves, rows_max * p.segs);
   p.cbytes = p.ev_per_batch * event_const_bytes(p.loglik != 0);
   p.lds_bytes = tiled_lds_layout(p.pitch, p.W, p.RY, p.acc32, p.ev_per_batch, p.loglik != 0, &p.lds_ev, &p.lds_off);
   p.batch_bytes = (int)(((unsigned)p.cbytes + 4u * (64u + kBlockTailWords) * (unsigned)p.waves + 255u) / 256u * 256u);
@@ -224,6 +225,7 @@ void plan_candidates(const jpet_geometry* g, double msz, double mdl, int64_t n, 
   Plan none;
   memset(&none, 0, sizeof(none));
   none.ntb = 1;
+  none.segs = 1;
   none.dt = 1.0;
   none.code = kPlanGeneric;
   const double pix = g->pixel;
@@ -232,13 +234,13 @@ void plan_candidates(const jpet_geometry* g, double msz, double mdl, int64_t n, 
   const int maxrow = (int)floor(chord_px) + 1;
   const int rows_max = (int)floor(2.0 * hy_px) + 1;
   const double tmax = 0.5 * g->L / g->R;               // |tan| of any valid event
-  int maxlen = 0;
+  int natural = 0;  // the smallest register cache that holds the longest row
   for (int c : {16, 32, 48, 64})
     if (maxrow <= c) {
-      maxlen = c;
+      natural = c;
       break;
     }
-  if (maxlen == 0 || rows_max > 64 * 16) {  // generic pass only
+  if (natural == 0 || rows_max > 64 * 16) {  // generic pass only
     out->push_back({none, 0.0});
     return;
   }
@@ -261,67 +263,80 @@ void plan_candidates(const jpet_geometry* g, double msz, double mdl, int64_t n, 
   // the second term being the staging of the image region and the flush of its accumulators
   // (about 1.6 pair evaluations per region pixel); items are the events over the events per item
   // plus, at most, one partial item per bin.
-  // (the log-likelihood pass, with its derivative terms, keeps 5 / 4 / 4 / 4)
-  const int simd_waves = loglik ? (maxlen <= 16 ? 5 : 4) : maxlen <= 16 ? 8 : maxlen <= 32 ? 6 : maxlen <= 48 ? 5 : 4;
-  // LDS per CU, the passes' static LDS (per-event denominators; the log-likelihood pass also its
-  // derivative sums), and the allocation granule: measured on gfx950, three workgroups of 51,984
-  // bytes each run on one CU but three of 54,032 bytes do not (the pass then runs 27% slower), so
-  // a workgroup's LDS is counted in whole 2 KB granules.
-  const size_t kLdsPerCU = 160 * 1024, kStatic = loglik ? 2 * 1024 : 1024, kGranule = 2048;
-  const double pairs_per_event = 3.14159265358979323846 * hy_px * (3.0 * msz / sqrt(2.0) / pix);
-  const double nn = (double)(n > 0 ? n : 1);
-  for (int waves : {8, 16}) {
-    if (rows_max > 64 * waves) continue;
-    for (int wgs = 1; wgs <= 4; ++wgs) {
-      const int occ = wgs * waves / 4;  // resident wavefronts per SIMD
-      if (occ > simd_waves) continue;
-      const size_t budget = kLdsPerCU / (size_t)wgs / kGranule * kGranule - kStatic;
-      const double occ_factor = pow(4.0 / (double)occ, 0.58) * (waves == 16 ? 1.1 : 1.0);
-      for (int acc32 = 0; acc32 <= 1; ++acc32) {
-        if (acc32 && !allow_acc32) continue;
-        for (int dti = 0; dti < kPlanDtCount; ++dti) {
-          const double dt = kPlanDt[dti];
-          // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
-          const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
-          const double hz = 3.0 * sqrt(0.5 * msz * msz + 0.25 * mdl * mdl * tau * tau);
-          const int HZ = (int)ceil(hz / pix + 1.0) + 1;
-          for (int ti = 0; ti < kPlanTileCount; ++ti) {
-            const int T = kPlanTile[ti];
-            // LDS: float image, then the accumulators, column-major with the row pitch rounded
-            // up to the bank alignment; masked reads up to maxlen columns past the image must stay
-            // in the accumulator array (W columns of 4 or 8 bytes)
-            const int RY = T + 2 * HY, W = T + 2 * HZ;
-            const int pitch = (RY + kBankAlign - 1) / kBankAlign * kBankAlign;
-            const size_t bytes =
-                tiled_lds_layout(pitch, W, RY, acc32, events_per_batch(waves, rows_max), loglik, nullptr, nullptr);
-            const int reach = acc32 ? W : 2 * W;
-            // thread words address columns with 8 bits and rows with 9 bits
-            if (bytes > budget || reach < maxlen || W > 256 || RY > 512) continue;
-            Plan p = none;
-            p.maxlen = maxlen;
-            p.HY = HY;
-            p.pitch = pitch;
-            p.waves = waves;
-            p.acc32 = acc32;
-            p.TY = T;
-            p.TZ = T;
-            p.HZ = HZ;
-            p.RY = RY;
-            p.W = W;
-            p.wgs = wgs;
-            p.loglik = loglik ? 1 : 0;
-            p.code = plan_code(waves, acc32, wgs, dti, ti);
-            if (dt != 0.0) {
-              p.ntb = (int)ceil(2.0 * tmax / dt);
-              if (p.ntb < 1) p.ntb = 1;
-              p.dt = dt;
-              p.tmin = -0.5 * dt * p.ntb;
+  // (the log-likelihood pass, with its derivative terms, keeps 5 / 4 / 4 / 4).  Rows longer than
+  // a cache of 16 or 32 may also be split into two segments, one thread each (x 1.3: the second
+  // row setups, the shorter segments and the lanes they leave idle; a prior, not a measurement,
+  // that keeps whole rows the model's choice wherever they fit and leaves split plans to timing).
+  for (int cache = 0; cache <= 2; ++cache) {
+    int maxlen = natural, segs = 1;
+    if (cache > 0) {
+      maxlen = cache == 1 ? 16 : 32;
+      if (!(maxrow > maxlen && maxrow <= 2 * maxlen)) continue;  // not needed, or too long to split in two
+      if (loglik) continue;                                      // the log-likelihood pass keeps whole rows
+      segs = 2;
+    }
+    const int simd_waves = loglik ? (maxlen <= 16 ? 5 : 4) : maxlen <= 16 ? 8 : maxlen <= 32 ? 6 : maxlen <= 48 ? 5 : 4;
+    // LDS per CU, the passes' static LDS (per-event denominators; the log-likelihood pass also its
+    // derivative sums), and the allocation granule: measured on gfx950, three workgroups of 51,984
+    // bytes each run on one CU but three of 54,032 bytes do not (the pass then runs 27% slower), so
+    // a workgroup's LDS is counted in whole 2 KB granules.
+    const size_t kLdsPerCU = 160 * 1024, kStatic = loglik ? 2 * 1024 : 1024, kGranule = 2048;
+    const double pairs_per_event = 3.14159265358979323846 * hy_px * (3.0 * msz / sqrt(2.0) / pix);
+    const double nn = (double)(n > 0 ? n : 1);
+    for (int waves : {8, 16}) {
+      if (rows_max * segs > 64 * waves) continue;
+      for (int wgs = 1; wgs <= 4; ++wgs) {
+        const int occ = wgs * waves / 4;  // resident wavefronts per SIMD
+        if (occ > simd_waves) continue;
+        const size_t budget = kLdsPerCU / (size_t)wgs / kGranule * kGranule - kStatic;
+        const double occ_factor = pow(4.0 / (double)occ, 0.58) * (waves == 16 ? 1.1 : 1.0) * (segs > 1 ? 1.3 : 1.0);
+        for (int acc32 = 0; acc32 <= 1; ++acc32) {
+          if (acc32 && !allow_acc32) continue;
+          for (int dti = 0; dti < kPlanDtCount; ++dti) {
+            const double dt = kPlanDt[dti];
+            // largest |t - t_c| / c inside a bin (no shear: |t| / c <= sin(atan(tmax)))
+            const double tau = dt == 0.0 ? tmax / sqrt(1.0 + tmax * tmax) : 0.5 * dt;
+            const double hz = 3.0 * sqrt(0.5 * msz * msz + 0.25 * mdl * mdl * tau * tau);
+            const int HZ = (int)ceil(hz / pix + 1.0) + 1;
+            for (int ti = 0; ti < kPlanTileCount; ++ti) {
+              const int T = kPlanTile[ti];
+              // LDS: float image, then the accumulators, column-major with the row pitch rounded
+              // up to the bank alignment; masked reads up to maxlen columns past the image must stay
+              // in the accumulator array (W columns of 4 or 8 bytes)
+              const int RY = T + 2 * HY, W = T + 2 * HZ;
+              const int pitch = (RY + kBankAlign - 1) / kBankAlign * kBankAlign;
+              const size_t bytes = tiled_lds_layout(pitch, W, RY, acc32, events_per_batch(waves, rows_max * segs),
+                                                    loglik, nullptr, nullptr);
+              const int reach = acc32 ? W : 2 * W;
+              // thread words address columns with 8 bits and rows with 9 bits
+              if (bytes > budget || reach < maxlen || W > 256 || RY > 512) continue;
+              Plan p = none;
+              p.maxlen = maxlen;
+              p.segs = segs;
+              p.HY = HY;
+              p.pitch = pitch;
+              p.waves = waves;
+              p.acc32 = acc32;
+              p.TY = T;
+              p.TZ = T;
+              p.HZ = HZ;
+              p.RY = RY;
+              p.W = W;
+              p.wgs = wgs;
+              p.loglik = loglik ? 1 : 0;
+              p.code = plan_code(waves, acc32, wgs, dti, ti, cache);
+              if (dt != 0.0) {
+                p.ntb = (int)ceil(2.0 * tmax / dt);
+                if (p.ntb < 1) p.ntb = 1;
+                p.dt = dt;
+                p.tmin = -0.5 * dt * p.ntb;
+              }
+              finish_plan(g, rows_max, n, p);
+              const double items = nn / p.ev_per_wg + (nn < p.nbins ? nn : (double)p.nbins);
+              const double cost = nn * pairs_per_event * occ_factor * (acc32 ? 0.82 : 1.0) +
+                                  1.6 * items * (double)pitch * (double)W;
+              out->push_back({p, cost});
             }
-            finish_plan(g, rows_max, n, p);
-            const double items = nn / p.ev_per_wg + (nn < p.nbins ? nn : (double)p.nbins);
-            const double cost = nn * pairs_per_event * occ_factor * (acc32 ? 0.82 : 1.0) +
-                                1.6 * items * (double)pitch * (double)W;
-            out->push_back({p, cost});
           }
         }
       }
@@ -343,6 +358,7 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, bool l
     Plan p;
     memset(&p, 0, sizeof(p));
     p.ntb = 1;
+    p.segs = 1;
     p.dt = 1.0;
     p.code = kPlanGeneric;
     return p;
@@ -638,6 +654,7 @@ int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_
   info->plan = p.code;
   info->workgroups_per_cu = p.tiled ? p.wgs : 0;
   info->accumulator_shift = p.tiled && p.acc32 ? p.acc_shift : 0;
+  info->row_segments = p.tiled ? p.segs : 1;
   return JPET_OK;
 }
 

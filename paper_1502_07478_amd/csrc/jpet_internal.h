@@ -112,7 +112,8 @@ struct Plan {
   int ntb, nty, ntz;    // bins along t, y, z
   int nbins;
   double tmin, dt;      // t bin b spans [tmin + b dt, tmin + (b+1) dt); ntb == 1: no shear
-  int maxlen;           // register cache length (16/32/48/64) >= longest ellipse row
+  int maxlen;           // register cache length (16/32/48/64): the longest row segment a thread holds
+  int segs;             // row segments per ellipse row, at most (1, or 2: longer rows are split)
   int waves;            // wavefronts per workgroup
   int acc32;            // 1: 32-bit LDS accumulators in 2^-acc_shift units
   int acc_shift;        // 32 - bits of the largest item size (events): no 32-bit slot overflows
@@ -139,21 +140,22 @@ inline int event_const_bytes(bool loglik) { return loglik ? (int)sizeof(EvConst)
 // otherwise bits 0-1 are the kind (1: binned pass with 8-wavefront workgroups, 2: with 16, 3: the
 // generic one-wavefront-per-event pass, all other bits 0), bit 2 selects 32-bit LDS
 // accumulators, bits 3-5 the workgroups resident per CU (1-4) the LDS region is sized for,
-// bits 6-8 the tan(theta~) bin width (index into kPlanDt) and bits 9-11 the square tile (index
-// into kPlanTile).
+// bits 6-8 the tan(theta~) bin width (index into kPlanDt), bits 9-11 the square tile (index
+// into kPlanTile) and bits 12-13 the register cache: 0 the smallest that holds the longest row,
+// 1 (2) rows split into segments of at most 16 (32) pixels.
 constexpr int kPlanDtCount = 6, kPlanTileCount = 5;
 constexpr double kPlanDt[kPlanDtCount] = {0.0, 0.4, 0.2, 0.1, 0.05, 0.025};
 constexpr int kPlanTile[kPlanTileCount] = {32, 24, 16, 12, 8};
 constexpr int32_t kPlanGeneric = 3;
-inline int32_t plan_code(int waves, int acc32, int wgs, int dt_index, int tile_index) {
-  return (waves == 16 ? 2 : 1) | (acc32 ? 4 : 0) | (wgs << 3) | (dt_index << 6) | (tile_index << 9);
+inline int32_t plan_code(int waves, int acc32, int wgs, int dt_index, int tile_index, int cache) {
+  return (waves == 16 ? 2 : 1) | (acc32 ? 4 : 0) | (wgs << 3) | (dt_index << 6) | (tile_index << 9) | (cache << 12);
 }
 // 1 when the code is well formed (not whether it fits a geometry)
 inline bool plan_code_valid(int32_t c) {
   if (c == 0 || c == kPlanGeneric) return true;
-  const int kind = c & 3, wgs = (c >> 3) & 7, dti = (c >> 6) & 7, ti = (c >> 9) & 7;
-  return kind >= 1 && kind <= 2 && wgs >= 1 && wgs <= 4 && dti < kPlanDtCount && ti < kPlanTileCount &&
-         (c >> 12) == 0;
+  const int kind = c & 3, wgs = (c >> 3) & 7, dti = (c >> 6) & 7, ti = (c >> 9) & 7, cache = (c >> 12) & 3;
+  return kind >= 1 && kind <= 2 && wgs >= 1 && wgs <= 4 && dti < kPlanDtCount && ti < kPlanTileCount && cache <= 2 &&
+         (c >> 14) == 0;
 }
 
 // Counters kept in the workspace (unsigned 64-bit).

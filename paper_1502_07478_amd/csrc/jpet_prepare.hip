@@ -242,14 +242,18 @@ __device__ EvRow event_row_constants(const Geo& g, const EventRec& e, int rbase,
 }
 
 // Batch blocks of the binned pass: one workgroup per item builds, for each batch of ev_per_batch
-// events, the per-event constants and the thread words.  Rows are given to threads so that a
-// wavefront holds rows of nearly equal length: each event's rows are cut into rings of 32 rows
-// around its central row (ring 0: the 32 central rows; ring k: 16 rows above and 16 below ring
-// k-1) and a remainder at its two tips.  Half-wavefront slots take the rings ordered by ring
-// index, then by event, so a wavefront pairs two rings at the same distance from their
-// ellipses' centres; the tips of all events fill the remaining threads.  Within a
-// half-wavefront the rows are consecutive, which keeps the pass's LDS accesses conflict-free.
+// events, the per-event constants and the thread words.  A thread owns one row segment of at most
+// the register cache's length: every ellipse row has a first segment, and when the plan splits
+// rows (p.segs = 2) each row longer than the cache also has a second one, its remaining pixels.
+// The segments of one level of one event form a "group" of consecutive rows.  Rows are given to
+// threads so that a wavefront holds rows of nearly equal length: each group's rows are cut into
+// rings of 32 rows around its central row (ring 0: the 32 central rows; ring k: 16 rows above and
+// 16 below ring k-1) and a remainder at its two tips.  Half-wavefront slots take the rings ordered
+// by ring index, then by group, so a wavefront pairs two rings at the same distance from their
+// ellipses' centres; the tips of all groups fill the remaining threads.  Within a half-wavefront
+// the rows are consecutive, which keeps the pass's LDS accesses free of bank conflicts.
 constexpr int kBuildBatch = 32;
+constexpr int kBuildGroups = 2 * kBuildBatch;
 constexpr int kBuildSlots = 64;
 
 __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const EventRec* __restrict__ evs,
@@ -257,9 +261,12 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
                                                         unsigned char* __restrict__ blocks,
                                                         unsigned long long* __restrict__ cnt) {
   __shared__ EventRec ev_s[kBuildBatch];
-  __shared__ int K_s[kBuildBatch], top_s[kBuildBatch];
-  __shared__ unsigned char slot_e[kBuildSlots], slot_k[kBuildSlots];
-  __shared__ int tip_cum[kBuildBatch + 1];
+  // groups: g < nb is event g's first segments over all its rows; nb + g its second segments,
+  // over the rows from its first to its last row longer than the register cache (none: 0 rows)
+  __shared__ int grp_r0[kBuildGroups], grp_n[kBuildGroups];
+  __shared__ int K_s[kBuildGroups], top_s[kBuildGroups];
+  __shared__ unsigned char slot_g[kBuildSlots], slot_k[kBuildSlots];
+  __shared__ int tip_cum[kBuildGroups + 1];
   __shared__ int nslots_s;
   __shared__ unsigned outside_s;
   if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;
@@ -277,17 +284,27 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
   if (tid == 0) outside_s = 0u;
   for (int e0 = 0, bi = 0; e0 < it.count; e0 += p.ev_per_batch, ++bi) {
     const int nb = min(p.ev_per_batch, it.count - e0);
+    const int ng = p.segs > 1 ? 2 * nb : nb;
     unsigned char* blk = blocks + (size_t)(it.batch + bi) * (size_t)p.batch_bytes;
     uint32_t* words = reinterpret_cast<uint32_t*>(blk + p.cbytes);
     __syncthreads();
     if (tid < nb) {
       const EventRec e = evs[it.start + e0 + tid];
       ev_s[tid] = e;
-      const int nrows = e.r1 - e.r0 + 1;
-      const int mrow = nrows >> 1;
-      const int K = min(mrow, nrows - mrow) >> 4;
-      K_s[tid] = K;
-      top_s[tid] = mrow - 16 * K;
+      grp_r0[tid] = 0;
+      grp_n[tid] = e.r1 - e.r0 + 1;
+      if (p.segs > 1) {  // the rows longer than the register cache
+        int first = -1, last = -2;
+        for (int i = e.r0; i <= e.r1; ++i) {
+          int klo, khi;
+          if (row_interval(g, e, i, &klo, &khi) && khi - klo + 1 > p.maxlen) {
+            if (first < 0) first = i - e.r0;
+            last = i - e.r0;
+          }
+        }
+        grp_r0[nb + tid] = first < 0 ? 0 : first;
+        grp_n[nb + tid] = last - first + 1 > 0 ? last - first + 1 : 0;
+      }
       if (p.loglik) {
         const float t = (float)e.t, c2 = (float)(e.c * e.c), u = (float)(g.u * e.su), w = (float)g.w,
                     fa = (float)g.fa;
@@ -316,16 +333,22 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
       }
     }
     __syncthreads();
-    if (tid < WAVE) {  // ring slots (ring-major, then event) and the tip prefix
-      const int K = tid < nb ? K_s[tid] : 0;
-      const int T = tid < nb ? (ev_s[tid].r1 - ev_s[tid].r0 + 1) - 32 * K : 0;
+    if (tid < WAVE) {  // ring slots (ring-major, then group) and the tip prefix
+      const int nrows = tid < ng ? grp_n[tid] : 0;
+      const int mrow = nrows >> 1;
+      const int K = min(mrow, nrows - mrow) >> 4;
+      const int T = nrows - 32 * K;
+      if (tid < ng) {
+        K_s[tid] = K;
+        top_s[tid] = mrow - 16 * K;
+      }
       const int Kmax = wave_max_i(K);
       int base_slot = 0;
       for (int k = 0; k < Kmax; ++k) {
         const unsigned long long msk = __ballot(K > k);
         const int before = __popcll(msk & ((1ull << lane) - 1ull));
         if (K > k) {
-          slot_e[base_slot + before] = (unsigned char)tid;
+          slot_g[base_slot + before] = (unsigned char)tid;
           slot_k[base_slot + before] = (unsigned char)k;
         }
         base_slot += __popcll(msk);
@@ -336,52 +359,62 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
         const int o = __shfl_up(incl, off, WAVE);
         if (lane >= off) incl += o;
       }
-      if (tid < nb) tip_cum[tid] = incl - T;
-      if (tid == nb - 1) tip_cum[nb] = incl;
+      if (tid < ng) tip_cum[tid] = incl - T;
+      if (tid == ng - 1) tip_cum[ng] = incl;
       if (tid == 0) nslots_s = base_slot;
     }
     __syncthreads();
     const int nslots = nslots_s;
-    int e = -1, ri = 0;
+    int gi = -1, ri = 0;  // group and row within the group
     if (tid < 32 * nslots) {
       const int sl = tid >> 5, l = tid & 31;
-      e = slot_e[sl];
+      gi = slot_g[sl];
       const int k = slot_k[sl];
-      const int mrow = (ev_s[e].r1 - ev_s[e].r0 + 1) >> 1;
+      const int mrow = grp_n[gi] >> 1;
       ri = k == 0 ? mrow - 16 + l : (l < 16 ? mrow - 16 * (k + 1) + l : mrow + 16 * k + (l - 16));
-    } else if (tid - 32 * nslots < tip_cum[nb]) {
+    } else if (tid - 32 * nslots < tip_cum[ng]) {
       const int q = tid - 32 * nslots;
-      int lo = 0, hi = nb - 1;
+      int lo = 0, hi = ng - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (tip_cum[mid] <= q) lo = mid; else hi = mid - 1;
       }
-      e = lo;
-      const int qq = q - tip_cum[e];
-      const int top = top_s[e];
-      ri = qq < top ? qq : ((ev_s[e].r1 - ev_s[e].r0 + 1) >> 1) + 16 * K_s[e] + (qq - top);
+      gi = lo;
+      const int qq = q - tip_cum[gi];
+      const int top = top_s[gi];
+      ri = qq < top ? qq : (grp_n[gi] >> 1) + 16 * K_s[gi] + (qq - top);
     }
     uint32_t word = 0u;
-    bool guard = false;  // this row may reach kappa <= 0: the pass tests every pixel
-    if (e >= 0) {
+    bool guard = false;  // this segment may reach kappa <= 0: the pass tests every pixel
+    if (gi >= 0) {
+      const int e = gi < nb ? gi : gi - nb;
       const EventRec ev = ev_s[e];
-      const int i = ev.r0 + ri;
+      const int i = ev.r0 + grp_r0[gi] + ri;
       int klo, khi;
       if (row_interval(g, ev, i, &klo, &khi)) {
-        const int rl = i - rbase;
-        const int kl = klo - shear_offset(g, tc, i) - kbase;
-        const int n = khi - klo + 1;
-        if (rl < 0 || rl >= p.RY || kl < 0 || kl + n > p.W || n > p.maxlen) {
-          atomicAdd(&outside_s, 1u);
-        } else {
-          word = ((uint32_t)kl << kWordCol) | ((uint32_t)rl << kWordRow) | ((uint32_t)n << kWordLen) |
-                 ((uint32_t)e << kWordEv);
-          // kappa is affine along the row: its smallest value is at one of the two ends; rows
-          // whose ends both keep a margin of 1e-3 of the first value can skip the test
-          double kf, ks;
-          (void)row_constants(g, ev, i, klo, &kf, &ks);
-          const double kend = kf + (double)(n - 1) * ks;
-          guard = !(kf > 1e-3 * fabs(kf) && kend > 1e-3 * fabs(kf));
+        int n = khi - klo + 1;
+        if (gi < nb) {  // first segment
+          if (n > p.maxlen && p.segs > 1) n = p.maxlen;
+        } else {        // second segment: the pixels past the first
+          klo += p.maxlen;
+          n -= p.maxlen;
+        }
+        if (n > 0) {
+          const int rl = i - rbase;
+          const int kl = klo - shear_offset(g, tc, i) - kbase;
+          if (rl < 0 || rl >= p.RY || kl < 0 || kl + n > p.W || n > p.maxlen) {
+            atomicAdd(&outside_s, 1u);
+          } else {
+            word = ((uint32_t)kl << kWordCol) | ((uint32_t)rl << kWordRow) | ((uint32_t)n << kWordLen) |
+                   ((uint32_t)e << kWordEv);
+            // kappa is affine along the row: its smallest value is at one of the segment's two
+            // ends; segments whose ends both keep a margin of 1e-3 of the first value can skip
+            // the test
+            double kf, ks;
+            (void)row_constants(g, ev, i, klo, &kf, &ks);
+            const double kend = kf + (double)(n - 1) * ks;
+            guard = !(kf > 1e-3 * fabs(kf) && kend > 1e-3 * fabs(kf));
+          }
         }
       }
     }

@@ -60,7 +60,7 @@ class LaunchInfo(ctypes.Structure):
         "events_per_batch", "events_per_workgroup", "accumulator_bits")] + [
         ("t_bin_width", ctypes.c_double), ("lds_bytes", ctypes.c_int64), ("max_workgroups", ctypes.c_int64),
         ("plan", ctypes.c_int32), ("workgroups_per_cu", ctypes.c_int32), ("accumulator_shift", ctypes.c_int32),
-        ("pad", ctypes.c_int32)]
+        ("row_segments", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -84,7 +84,10 @@ def test_position_dependent_sigma_z(lib):
     not defined for it."""
     g0 = jpet.geometry(**GOOD)
     g1 = jpet.geometry(**GOOD, sigma_z_edge=0.4)
-    assert ws_size(g1, 10**6)[1] > ws_size(g0, 10**6)[1]
+    code = jpet.launch_info(g0, 10**6)["plan"]
+    i0 = jpet.launch_info(jpet.with_plan(g0, code), 10**6)
+    i1 = jpet.launch_info(jpet.with_plan(g1, code), 10**6)
+    assert i1["halo_cols"] > i0["halo_cols"] and i1["lds_bytes"] > i0["lds_bytes"]
     b = ctypes.c_size_t(0)
     assert lib.jpet_loglik_workspace_size(ctypes.byref(g1), None, 10, ctypes.byref(b)) == jpet.JPET_ENOTSUP
     assert lib.jpet_loglik_workspace_size(ctypes.byref(g0), None, 10, ctypes.byref(b)) == jpet.JPET_OK
@@ -185,7 +188,8 @@ def test_plan_candidates_and_named_plans(lib):
     # the generic pass can always be named
     assert jpet.launch_info(jpet.with_plan(g, 3), n)["binned"] == 0
     # malformed codes
-    for bad in (-1, 4, 1 | (5 << 3), 1 | (1 << 3) | (6 << 6), 1 | (1 << 3) | (5 << 9), 1 | (1 << 3) | (1 << 12), 7):
+    for bad in (-1, 4, 1 | (5 << 3), 1 | (1 << 3) | (6 << 6), 1 | (1 << 3) | (5 << 9), 1 | (1 << 3) | (3 << 12),
+                1 | (1 << 3) | (1 << 14), 7):
         assert ws_size(jpet.with_plan(g, bad), n)[0] == jpet.JPET_EINVAL, bad
     # well formed but too large for the LDS: 64-bit accumulators, one 32-row tile, no shear,
     # four workgroups per CU
@@ -199,9 +203,20 @@ def test_plan_candidates_and_named_plans(lib):
     acc32 = next(code for code, _ in cands if code & 4)
     assert lib.jpet_loglik_workspace_size(ctypes.byref(jpet.with_plan(g, acc32)), None, n,
                                           ctypes.byref(b)) == jpet.JPET_EDOMAIN
-    # rows longer than the register cache: only the generic pass
+    # rows of more than 64 pixels (twice the largest cache that is split): only the generic pass
     fine = jpet.geometry(**{**GOOD, "sigma_z": 12.0, "pixel": 0.5})
     assert jpet.plan_candidates(fine, 1000) == [(3, 0.0)]
+    # rows of 33..64 pixels: whole rows in a 48/64 cache, or split in two 32-pixel segments
+    mid = jpet.geometry(**{**GOOD, "sigma_z": 10.0, "pixel": 0.9})
+    mc = jpet.plan_candidates(mid, 10**6)
+    caches = {(code >> 12) & 3 for code, _ in mc}
+    assert caches == {0, 2}
+    split = next(code for code, _ in mc if (code >> 12) & 3 == 2)
+    info = jpet.launch_info(jpet.with_plan(mid, split), 10**6)
+    assert info["row_cache"] == 32 and info["row_segments"] == 2
+    whole = next(code for code, _ in mc if (code >> 12) & 3 == 0)
+    info = jpet.launch_info(jpet.with_plan(mid, whole), 10**6)
+    assert info["row_cache"] in (48, 64) and info["row_segments"] == 1
 
 
 def test_binding_requires_built_library(monkeypatch, tmp_path):
