@@ -26,7 +26,8 @@
  * Memory: every array argument is DEVICE memory on the current HIP device, owned by the
  * caller, unless the argument says "host".  The library allocates no device memory in
  * any entry point below; scratch space is the caller's workspace.  It keeps no pointer
- * after a call returns.
+ * after a call returns, except in a batched graph (jpet_mlem_batched_graph_create), whose
+ * captured launches hold the batch's pointers and whose instantiation is the HIP runtime's.
  *
  * Streams: `stream` is a hipStream_t (NULL = the legacy default stream).  Work is enqueued
  * asynchronously; outputs are valid once the stream has been synchronised, except that an
@@ -230,9 +231,14 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
                      size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream);
 
 /* Batched reconstruction: many independent list-mode MLEM problems (each with its own geometry,
- * resolution, event list, sensitivity and image) advanced together: per iteration, one event-pass
- * launch for each group of instances that share a kernel configuration (at most a handful).  Each instance's result is that of jpet_mlem_iterate on it alone
- * (to FP32 rounding of the denominators: events are grouped into workgroup batches the same way).
+ * resolution, event list, sensitivity and image) advanced together.  Per iteration one persistent
+ * event-pass launch serves every instance that fits the binned pass: its workgroups, as many as
+ * stay resident, pull (instance, workgroup item) work from a counter, the instances' items in
+ * order of decreasing size, until all are done; instances that fit only the generic pass get their
+ * own launches.  All binned instances use one kernel configuration (see jpet_geometry.plan: codes
+ * named for a batch must share 8-wavefront workgroups, 32-bit accumulators, the residency per CU
+ * and a register cache of at most 32 pixels, else JPET_EDOMAIN).  Each instance's result is that of
+ * jpet_mlem_iterate on it alone with the same plan, to FP32 rounding of the denominators.
  * Host struct; pointers as for jpet_mlem_iterate. */
 typedef struct jpet_instance {
   jpet_geometry g;
@@ -252,12 +258,27 @@ int jpet_mlem_batched_prepare(const jpet_instance* inst, int32_t count, void* ws
 /* n_iter MLEM iterations of every instance, in place on each rho.  flags: 0 or JPET_WS_PREPARED
  * (the workspace holds jpet_mlem_batched_prepare's output for the same instance array: same
  * geometries, event pointers and counts).  stats: host array of count entries, or NULL; entry k
- * describes instance k (the call then synchronises).  Instances must not share rho arrays.
- * The work is ordered on stream as usual; inside each iteration, groups of instances that use
- * different kernels run on up to three side streams that the library creates once per device
- * (default priority) and forks from and joins back to stream with events. */
+ * describes instance k (the call then synchronises).  Instances must not share rho arrays. */
 int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t n_iter, void* ws, size_t ws_bytes,
                               uint32_t flags, jpet_stats* stats, void* stream);
+
+/* The same n_iter iterations captured once into a HIP graph (a reset, the persistent pass, any
+ * generic passes and the update per iteration, all kernels), for repeated launches with no host
+ * work.  Creating the graph prepares the instances (unless JPET_WS_PREPARED) and writes the batch's
+ * instance table and work list into the workspace on stream, in stream order, before capturing;
+ * each launch then runs n_iter iterations on the images as they are at that point in the stream.
+ * The instance array's device pointers, the workspace and the event lists must stay valid and
+ * unchanged while the graph exists; a later jpet_mlem_batched_iterate or a graph of another
+ * instance array on the same workspace rewrites the table (create the graph again after it).
+ * The graph object is host memory and runtime state of the library's, released by
+ * jpet_mlem_batched_graph_destroy.  n_iter >= 1; *out (host) receives the graph. */
+typedef struct jpet_batched_graph jpet_batched_graph;
+int jpet_mlem_batched_graph_create(const jpet_instance* inst, int32_t count, int32_t n_iter, void* ws,
+                                   size_t ws_bytes, uint32_t flags, void* stream, jpet_batched_graph** out);
+/* Enqueues one launch of the graph (n_iter iterations) on stream. */
+int jpet_mlem_batched_graph_launch(jpet_batched_graph* graph, void* stream);
+/* Releases the graph (NULL is allowed); it must not be executing. */
+int jpet_mlem_batched_graph_destroy(jpet_batched_graph* graph);
 
 /* Launch shape the library picks for jpet_mlem_iterate on this geometry and event count
  * (diagnostics and tuning reports).  Host output. */

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <new>
 #include <utility>
 #include <vector>
 
@@ -21,30 +22,6 @@ thread_local int g_last_hip_error = 0;
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
-
-// Side streams on which the kernel groups of a batched event pass run side by side, so that one
-// group's last workgroups overlap the next group's first ones.  Created once per device, at the
-// default priority, and kept until the process ends; calls fork them from and join them to their
-// own stream with events, so calls on different streams stay ordered.
-constexpr int kSideStreams = 3;
-std::mutex g_side_mu;
-std::vector<std::vector<hipStream_t>> g_side;
-
-hipError_t side_streams(hipStream_t** out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  std::lock_guard<std::mutex> lk(g_side_mu);
-  if ((int)g_side.size() <= dev) g_side.resize(dev + 1);
-  std::vector<hipStream_t>& v = g_side[dev];
-  while ((int)v.size() < kSideStreams) {
-    hipStream_t s = nullptr;
-    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return e;
-    v.push_back(s);
-  }
-  *out = v.data();
-  return hipSuccess;
-}
 
 void prof_forget_locked() {
   for (auto& pr : g_prof_events) {
@@ -403,44 +380,66 @@ size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Work
   return off;
 }
 
-// Layout of a batched workspace: the instance table, then one ordinary workspace per instance.
-// Each instance keeps its own plan; instances whose plans share a kernel (register-cache length,
-// wavefronts per workgroup, accumulator width) form a group served by one launch per iteration,
-// with the group's largest LDS region.  Within a group the table is sorted by estimated work per
-// workgroup, heaviest first, so that the longest workgroups start earliest.
-struct BatchGroup {
+// Layout of a batched workspace: the instance table, one work counter per class, then one
+// ordinary workspace per instance.  Every instance that fits the binned pass takes the plan its
+// geometry names or the cost model's cheapest plan with 32-bit accumulators and a register cache
+// of at most 32 pixels (longer rows are split into two segments).  Instances whose plans share the
+// wavefronts per workgroup and the workgroups resident per CU form a class, served by one
+// persistent launch per iteration with the class's largest LDS region and register cache; a batch
+// of like instances is one class.  Within a class the table lists the instances heaviest workgroup
+// item first, so that the longest items are pulled earliest.  Instances that fit only the generic
+// pass follow the classes, with their own launches.
+struct BatchClass {
   int first = 0, count = 0;  // table positions
-  int maxlen = 0, waves = 0, acc32 = 0;
+  int maxlen = 0, waves = 0, wgs = 0;
   size_t lds = 0;
-  int64_t grid = 0;
 };
 
 struct BatchLayout {
-  std::vector<BatchGroup> group;
-  std::vector<Plan> plan;      // per instance
-  std::vector<size_t> off;     // per instance: byte offset of its workspace
-  std::vector<int> order;      // table position -> instance
-  std::vector<int64_t> begin;  // per instance: first workgroup in its group's grid
+  std::vector<Plan> plan;       // per instance
+  std::vector<size_t> off;      // per instance: byte offset of its workspace
+  std::vector<int> order;       // table position -> instance
+  std::vector<BatchClass> cls;  // the persistent launches
   int64_t max_npix = 0;
+  size_t work_off = 0;          // BatchWork[cls.size()]
   size_t total = 0;
-  bool invalid = false;  // an instance names a plan that does not fit its geometry
+  bool invalid = false;         // a named plan does not fit its geometry or the batched pass
 };
+
+static bool batchable(const Plan& p) { return p.tiled && p.acc32 && p.maxlen <= 32 && !p.loglik; }
 
 BatchLayout batch_layout(const jpet_instance* inst, int count) {
   BatchLayout L;
   L.plan.resize(count);
   L.off.resize(count);
-  L.begin.resize(count);
   std::vector<double> work(count, 0.0);
-  std::vector<int> key(count, 0);
+  std::vector<int> key(count, 1 << 30);  // class key; generic instances last
+  std::vector<PlanCand> cand;
   for (int k = 0; k < count; ++k) {
     const jpet_geometry& g = inst[k].g;
-    const Plan p = make_plan(&g, g.sigma_z, g.sigma_dl, inst[k].n);
+    Plan p;
+    if (g.plan != 0) {
+      p = make_plan(&g, g.sigma_z, g.sigma_dl, inst[k].n);
+      if (p.invalid || (p.tiled && !batchable(p))) {
+        L.invalid = true;
+        return L;
+      }
+    } else {
+      plan_candidates(&g, g.sigma_z, g.sigma_dl, inst[k].n, false, &cand);
+      p = cand[0].p;  // the generic pass when no binned plan fits
+      for (const PlanCand& x : cand)  // sorted by cost: the first batchable one
+        if (batchable(x.p)) {
+          p = x.p;
+          break;
+        }
+      if (p.tiled && !batchable(p)) {  // binned plans fit, none with a cache of 32 or less
+        L.invalid = true;
+        return L;
+      }
+    }
     L.plan[k] = p;
-    if (p.invalid) L.invalid = true;
-    // group key: generic instances last
-    key[k] = p.tiled ? (p.maxlen * 100 + p.waves + (p.acc32 ? 10000 : 0)) : 1 << 30;
     if (p.tiled) {
+      key[k] = p.waves * 8 + p.wgs;
       // pixels of a typical ellipse (App. B half sizes at theta = 0) times events per workgroup
       work[k] = (1.5 * g.sigma_dl / g.pixel) * (3.0 * g.sigma_z / sqrt(2.0) / g.pixel) * p.ev_per_wg;
     }
@@ -456,22 +455,23 @@ BatchLayout batch_layout(const jpet_instance* inst, int count) {
   for (int t = 0; t < count; ++t) {
     const int k = L.order[t];
     const Plan& p = L.plan[k];
-    if (!p.tiled) continue;
-    if (L.group.empty() || key[L.order[L.group.back().first]] != key[k]) {
-      BatchGroup G;
-      G.first = t;
-      G.maxlen = p.maxlen;
-      G.waves = p.waves;
-      G.acc32 = p.acc32;
-      L.group.push_back(G);
+    if (!p.tiled) break;
+    if (L.cls.empty() || key[L.order[L.cls.back().first]] != key[k]) {
+      BatchClass c;
+      c.first = t;
+      c.waves = p.waves;
+      c.wgs = p.wgs;
+      L.cls.push_back(c);
     }
-    BatchGroup& G = L.group.back();
-    ++G.count;
-    if (p.lds_bytes > G.lds) G.lds = p.lds_bytes;
-    L.begin[k] = G.grid;
-    G.grid += p.max_items;
+    BatchClass& c = L.cls.back();
+    ++c.count;
+    c.maxlen = p.maxlen > c.maxlen ? p.maxlen : c.maxlen;
+    if (p.lds_bytes > c.lds) c.lds = p.lds_bytes;
   }
+  for (BatchClass& c : L.cls) c.maxlen = c.maxlen <= 16 ? 16 : 32;
   size_t off = align_up(sizeof(BatchInst) * (size_t)count, 256);
+  L.work_off = off;
+  off = align_up(off + sizeof(BatchWork) * (L.cls.size() > 0 ? L.cls.size() : 1), 256);
   for (int k = 0; k < count; ++k) {
     L.off[k] = off;
     off = align_up(off + workspace_layout(L.plan[k], inst[k].n, npix_of(&inst[k].g), nullptr, nullptr), 256);
@@ -868,25 +868,16 @@ int jpet_mlem_batched_prepare(const jpet_instance* inst, int32_t count, void* ws
   return JPET_OK;
 }
 
-int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t n_iter, void* ws, size_t ws_bytes,
-                              uint32_t flags, jpet_stats* stats, void* stream) {
-  if (n_iter < 0 || (flags & ~JPET_WS_PREPARED)) return JPET_EINVAL;
-  BatchLayout L;
-  std::vector<Workspace> w;
-  int rc = batched_carve(inst, count, ws, ws_bytes, &L, &w);
-  if (rc) return rc;
-  hipStream_t st = (hipStream_t)stream;
-  std::vector<Geo> geo(count);
-  for (int k = 0; k < count; ++k) geo[k] = make_geo(&inst[k].g, inst[k].g.sigma_z, inst[k].g.sigma_dl);
-  if (!(flags & JPET_WS_PREPARED)) {
-    for (int k = 0; k < count; ++k) {
-      rc = do_prepare(geo[k], L.plan[k], inst[k].events, inst[k].n, w[k], st);
-      if (rc) return rc;
-    }
-  }
-  // the instance table (in table order), written by small launches so that it stays stream-ordered
+}  // extern "C"
+
+// The setup of a batch's iterations, in stream order: the instance table, each binned instance's
+// first work index (from the items its preparation produced) and cleared accumulators.
+static int batched_setup(const jpet_instance* inst, int32_t count, const BatchLayout& L,
+                         const std::vector<Workspace>& w, const std::vector<Geo>& geo, void* ws, hipStream_t st) {
   BatchInst* table = reinterpret_cast<BatchInst*>(ws);
+  BatchWork* work = reinterpret_cast<BatchWork*>((char*)ws + L.work_off);
   hipError_t e;
+  // written by small launches (by-value arguments) so that it stays stream-ordered
   for (int t0 = 0; t0 < count; t0 += kInstPerWrite) {
     InstWrite iw;
     memset(&iw, 0, sizeof(iw));
@@ -899,7 +890,10 @@ int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t 
       b.p = L.plan[k];
       b.tiled = L.plan[k].tiled;
       b.index = k;
-      b.item_begin = L.begin[k];
+      b.item_begin = 0;
+      b.cls = -1;
+      for (int c = 0; c < (int)L.cls.size(); ++c)
+        if (t0 + j >= L.cls[c].first && t0 + j < L.cls[c].first + L.cls[c].count) b.cls = c;
       b.n = inst[k].n;
       b.blocks = w[k].batches;
       b.items = w[k].items;
@@ -910,50 +904,48 @@ int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t 
     }
     if ((e = launch_write_insts(iw, table, st)) != hipSuccess) return hip_fail(e);
   }
+  if ((e = launch_batched_work(table, count, work, (int)L.cls.size(), st)) != hipSuccess) return hip_fail(e);
   for (int k = 0; k < count; ++k)
     if ((e = launch_fill_u64(w[k].acc, npix_of(&inst[k].g), st)) != hipSuccess) return hip_fail(e);
-  // groups after the first run on side streams (forked from and joined to st every iteration)
-  const int nside = std::min<int>(kSideStreams, (int)L.group.size() - 1);
-  hipStream_t* side = nullptr;
-  hipEvent_t fork = nullptr, join[kSideStreams] = {};
-  if (nside > 0) {
-    if ((e = side_streams(&side)) != hipSuccess) return hip_fail(e);
-    if ((e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
-    for (int i = 0; i < nside; ++i)
-      if ((e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
-  }
-  struct EventGuard {  // recorded events may still be pending: the runtime releases them when done
-    hipEvent_t* f;
-    hipEvent_t* j;
-    int n;
-    ~EventGuard() {
-      if (*f) (void)hipEventDestroy(*f);
-      for (int i = 0; i < n; ++i)
-        if (j[i]) (void)hipEventDestroy(j[i]);
-    }
-  } guard{&fork, join, nside};
+  return JPET_OK;
+}
+
+// The device's compute units (the persistent launches' grids are a multiple of them).
+static int device_cus(int* cus) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e);
+  return JPET_OK;
+}
+
+// n_iter iterations of a set-up batch: per iteration the counters' reset, one persistent pass per
+// class over its instances' items, the generic instances' passes and the pixel update of all.
+static int batched_iterations(const jpet_instance* inst, int32_t count, int32_t n_iter, const BatchLayout& L,
+                              const std::vector<Workspace>& w, const std::vector<Geo>& geo, void* ws, int cus,
+                              bool timing, hipStream_t st) {
+  BatchInst* table = reinterpret_cast<BatchInst*>(ws);
+  BatchWork* work = reinterpret_cast<BatchWork*>((char*)ws + L.work_off);
+  hipError_t e;
   for (int it = 0; it < n_iter; ++it) {
-    if ((e = launch_batched_reset(table, count, st)) != hipSuccess) return hip_fail(e);
-    rc = timed(
-        [&] {
-          hipError_t r = hipSuccess;
-          if (nside > 0) {
-            r = hipEventRecord(fork, st);
-            for (int i = 0; i < nside && r == hipSuccess; ++i) r = hipStreamWaitEvent(side[i], fork, 0);
-          }
-          for (size_t gi = 0; gi < L.group.size() && r == hipSuccess; ++gi) {
-            const BatchGroup& G = L.group[gi];
-            hipStream_t sg = gi == 0 ? st : side[(gi - 1) % nside];
-            r = launch_event_pass_batched(table + G.first, G.count, G.maxlen, G.waves, G.acc32, G.lds, G.grid, sg);
-          }
-          for (int i = 0; i < nside && r == hipSuccess; ++i) {
-            r = hipEventRecord(join[i], side[i]);
-            if (r == hipSuccess) r = hipStreamWaitEvent(st, join[i], 0);
-          }
-          return r;
-        },
-        st);
-    if (rc) return rc;
+    if ((e = launch_batched_reset(table, count, work, (int)L.cls.size(), st)) != hipSuccess) return hip_fail(e);
+    if (!L.cls.empty()) {
+      auto pass = [&] {
+        hipError_t r = hipSuccess;
+        for (size_t c = 0; c < L.cls.size() && r == hipSuccess; ++c) {
+          const BatchClass& C = L.cls[c];
+          r = launch_event_pass_persistent(table + C.first, C.count, work + c, C.maxlen, C.waves, C.lds, cus * C.wgs,
+                                           st);
+        }
+        return r;
+      };
+      if (timing) {
+        const int rc = timed(pass, st);
+        if (rc) return rc;
+      } else if ((e = pass()) != hipSuccess) {
+        return hip_fail(e);
+      }
+    }
     for (int k = 0; k < count; ++k) {
       if (L.plan[k].tiled) continue;
       if ((e = launch_event_pass(geo[k], L.plan[k], inst[k].n, w[k], inst[k].rho, st)) != hipSuccess)
@@ -961,12 +953,117 @@ int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t 
     }
     if ((e = launch_update_batched(table, count, L.max_npix, st)) != hipSuccess) return hip_fail(e);
   }
+  return JPET_OK;
+}
+
+// A batch, validated and carved, with its geometries; prepared (unless flagged as prepared) and set
+// up for iterating on stream st.
+static int batched_begin(const jpet_instance* inst, int32_t count, void* ws, size_t ws_bytes, uint32_t flags,
+                         hipStream_t st, BatchLayout* L, std::vector<Workspace>* w, std::vector<Geo>* geo,
+                         int* cus) {
+  int rc = batched_carve(inst, count, ws, ws_bytes, L, w);
+  if (rc) return rc;
+  geo->resize(count);
+  for (int k = 0; k < count; ++k) (*geo)[k] = make_geo(&inst[k].g, inst[k].g.sigma_z, inst[k].g.sigma_dl);
+  if (!(flags & JPET_WS_PREPARED)) {
+    for (int k = 0; k < count; ++k) {
+      rc = do_prepare((*geo)[k], L->plan[k], inst[k].events, inst[k].n, (*w)[k], st);
+      if (rc) return rc;
+    }
+  }
+  if ((rc = device_cus(cus))) return rc;
+  for (const BatchClass& C : L->cls) {
+    const hipError_t e = set_persistent_lds(C.maxlen, C.waves, C.lds);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return batched_setup(inst, count, *L, *w, *geo, ws, st);
+}
+
+struct jpet_batched_graph {
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+  int32_t n_iter = 0;
+};
+
+extern "C" {
+
+int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t n_iter, void* ws, size_t ws_bytes,
+                              uint32_t flags, jpet_stats* stats, void* stream) {
+  if (n_iter < 0 || (flags & ~JPET_WS_PREPARED)) return JPET_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  BatchLayout L;
+  std::vector<Workspace> w;
+  std::vector<Geo> geo;
+  int cus = 0;
+  int rc = batched_begin(inst, count, ws, ws_bytes, flags, st, &L, &w, &geo, &cus);
+  if (rc) return rc;
+  rc = batched_iterations(inst, count, n_iter, L, w, geo, ws, cus, true, st);
+  if (rc) return rc;
   if (stats) {
     for (int k = 0; k < count; ++k) {
       rc = read_stats(w[k], inst[k].n, &stats[k], st);
       if (rc) return rc;
     }
   }
+  return JPET_OK;
+}
+
+int jpet_mlem_batched_graph_create(const jpet_instance* inst, int32_t count, int32_t n_iter, void* ws,
+                                   size_t ws_bytes, uint32_t flags, void* stream, jpet_batched_graph** out) {
+  if (!out || n_iter < 1 || (flags & ~JPET_WS_PREPARED)) return JPET_EINVAL;
+  *out = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  BatchLayout L;
+  std::vector<Workspace> w;
+  std::vector<Geo> geo;
+  int cus = 0;
+  int rc = batched_begin(inst, count, ws, ws_bytes, flags, st, &L, &w, &geo, &cus);
+  if (rc) return rc;
+  // capture the iterations on a stream of the library's own, at the default priority
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e);
+  hipGraph_t graph = nullptr;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = batched_iterations(inst, count, n_iter, L, w, geo, ws, cus, false, cs);
+    e = hipStreamEndCapture(cs, &graph);
+  }
+  (void)hipStreamDestroy(cs);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e);
+  jpet_batched_graph* gr = new (std::nothrow) jpet_batched_graph;
+  if (!gr) {
+    (void)hipGraphExecDestroy(exec);
+    return JPET_EINVAL;
+  }
+  gr->exec = exec;
+  gr->n_iter = n_iter;
+  (void)hipGetDevice(&gr->device);
+  *out = gr;
+  return JPET_OK;
+}
+
+int jpet_mlem_batched_graph_launch(jpet_batched_graph* gr, void* stream) {
+  if (!gr || !gr->exec) return JPET_EINVAL;
+  const hipError_t e = hipGraphLaunch(gr->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return JPET_OK;
+}
+
+int jpet_mlem_batched_graph_destroy(jpet_batched_graph* gr) {
+  if (!gr) return JPET_OK;
+  hipError_t e = hipSuccess;
+  if (gr->exec) e = hipGraphExecDestroy(gr->exec);
+  delete gr;
+  if (e != hipSuccess) return hip_fail(e);
   return JPET_OK;
 }
 

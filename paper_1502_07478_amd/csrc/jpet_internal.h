@@ -203,7 +203,9 @@ struct BatchInst {
   Plan p;
   int32_t tiled;              // 1: binned pass inside the batched launch; 0: generic pass, launched apart
   int32_t index;              // position in the caller's instance array
-  int64_t item_begin;         // first workgroup of this instance in the batched grid
+  int32_t cls;                // the persistent launch (class) serving it, -1: none
+  int32_t pad;
+  int64_t item_begin;         // its first work index within its class
   int64_t n;                  // events
   const unsigned char* blocks;
   const BinItem* items;
@@ -211,6 +213,13 @@ struct BatchInst {
   const float* s;             // sensitivity or null
   unsigned long long* acc;
   unsigned long long* cnt;
+};
+
+// Work counter of a batched iteration's persistent pass.
+struct BatchWork {
+  unsigned next;   // next work index, reset every iteration
+  unsigned total;  // workgroup items of all binned instances
+  unsigned pad[2];
 };
 
 constexpr int kInstPerWrite = 6;  // instances written per table-writing launch (by-value kernel argument)
@@ -256,9 +265,15 @@ hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_update(const Geo& g, const float* s, float* rho, const Workspace& ws, hipStream_t st);
 // batched: table of count instances in device memory; grid = total workgroups of the tiled ones
 hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t st);
-hipError_t launch_batched_reset(const BatchInst* table, int count, hipStream_t st);
-hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxlen, int waves, int acc32,
-                                     size_t lds_bytes, int64_t grid, hipStream_t st);
+hipError_t launch_batched_reset(const BatchInst* table, int count, BatchWork* work, int nclasses, hipStream_t st);
+hipError_t launch_batched_work(BatchInst* table, int count, BatchWork* work, int nclasses, hipStream_t st);
+// the persistent pass over one class of a batch (table: the class's entries): 32-bit accumulators,
+// register cache maxlen (16 or 32), waves (8 or 16) wavefronts per workgroup, grid = resident
+// workgroups
+hipError_t launch_event_pass_persistent(const BatchInst* table, int count, BatchWork* work, int maxlen, int waves,
+                                        size_t lds_bytes, int grid, hipStream_t st);
+// raises a persistent pass's dynamic LDS limit (call before launching or capturing it)
+hipError_t set_persistent_lds(int maxlen, int waves, size_t lds_bytes);
 hipError_t launch_update_batched(const BatchInst* table, int count, int64_t max_npix, hipStream_t st);
 hipError_t launch_loglik(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
                          const float* s, float* D_out, float* grad_rho, double* out3, hipStream_t st);

@@ -594,26 +594,70 @@ __global__ void __launch_bounds__(WAVES * 64, MAXLEN <= 16 ? 5 : 4) k_loglik_til
                                                 red, nullptr);
 }
 
-// The same pass over many independent reconstructions in one launch: the grid is the
-// concatenation of the instances' work lists (table sorted by item_begin); each workgroup finds
-// its instance by binary search.
-template <int MAXLEN, int WAVES, bool ACC32>
-__global__ void __launch_bounds__(WAVES * 64, 4) k_event_pass_batched(const BatchInst* __restrict__ inst,
-                                                                      int count) {
+// The same pass over many independent reconstructions, persistent: the grid is as many
+// workgroups as stay resident, and each workgroup pulls work indices from a counter until the
+// batch's items run out.  Work index w is item w - item_begin of the last instance (in table order,
+// heaviest items first) whose item_begin <= w.  The region's row pitch varies between instances;
+// each common pitch has its own compile-time copy of the pass (immediate LDS offsets).
+template <int MAXLEN, int WAVES>
+__global__ void __launch_bounds__(WAVES * 64, pass_waves_per_simd<MAXLEN>())
+    k_event_pass_persistent(const BatchInst* __restrict__ inst, int count, BatchWork* __restrict__ work) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ PassShared ps;
-  const int64_t b = blockIdx.x;
-  int lo = 0, hi = count - 1;  // last instance whose item_begin <= b
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (inst[mid].item_begin <= b) lo = mid;
-    else hi = mid - 1;
+  __shared__ unsigned w_s;
+  const unsigned total = work->total;
+  for (;;) {
+    // w_s was last read before the previous item's barriers; every thread of the workgroup has
+    // left that item's LDS before the barrier below lets the next item start
+    if (threadIdx.x == 0) w_s = atomicAdd(&work->next, 1u);
+    __syncthreads();
+    const unsigned w = w_s;
+    if (w >= total) break;  // uniform over the workgroup
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (inst[mid].item_begin <= (int64_t)w) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchInst& I = inst[lo];
+    const BinItem it = I.items[(int64_t)w - I.item_begin];
+    switch (I.p.pitch) {
+      case 64:
+        event_pass_item<MAXLEN, WAVES, false, true, 64>(I.g, I.p, I.blocks, it, I.rho, I.acc, I.cnt, smem, ps,
+                                                        nullptr, nullptr, nullptr, nullptr);
+        break;
+      case 128:
+        event_pass_item<MAXLEN, WAVES, false, true, 128>(I.g, I.p, I.blocks, it, I.rho, I.acc, I.cnt, smem, ps,
+                                                         nullptr, nullptr, nullptr, nullptr);
+        break;
+      case 256:
+        event_pass_item<MAXLEN, WAVES, false, true, 256>(I.g, I.p, I.blocks, it, I.rho, I.acc, I.cnt, smem, ps,
+                                                         nullptr, nullptr, nullptr, nullptr);
+        break;
+      default:
+        event_pass_item<MAXLEN, WAVES, false, true, 0>(I.g, I.p, I.blocks, it, I.rho, I.acc, I.cnt, smem, ps,
+                                                       nullptr, nullptr, nullptr, nullptr);
+        break;
+    }
   }
-  const BatchInst& I = inst[lo];
-  const int64_t local = b - I.item_begin;
-  if (!I.tiled || local >= (int64_t)I.cnt[C_ITEMS]) return;
-  event_pass_item<MAXLEN, WAVES, false, ACC32, 0>(I.g, I.p, I.blocks, I.items[local], I.rho, I.acc, I.cnt, smem, ps,
-                                                 nullptr, nullptr, nullptr, nullptr);
+}
+
+// Work lists of a batch (one thread, after the preparation): each binned instance's first work
+// index within its class, in table order, from the items its preparation produced, and each
+// class's total.
+__global__ void k_batched_work(BatchInst* __restrict__ table, int count, BatchWork* __restrict__ work,
+                               int nclasses) {
+  if (threadIdx.x != 0) return;
+  for (int c = 0; c < nclasses; ++c) {
+    work[c].total = 0u;
+    work[c].next = 0u;
+  }
+  for (int k = 0; k < count; ++k) {
+    const int c = table[k].cls;
+    if (c < 0) continue;
+    table[k].item_begin = (int64_t)work[c].total;
+    work[c].total += (unsigned)table[k].cnt[C_ITEMS];
+  }
 }
 
 // Generic pass for geometries whose rows or regions do not fit the tiled pass: one wavefront per
@@ -741,26 +785,20 @@ hipError_t launch_tiled(const Geo& g, const Plan& p, const Workspace& ws, const 
   return hipGetLastError();
 }
 
-template <int MAXLEN, int WAVES, bool ACC32>
-hipError_t launch_batched(const BatchInst* table, int count, size_t lds_bytes, int64_t grid, hipStream_t st) {
-  auto kern = k_event_pass_batched<MAXLEN, WAVES, ACC32>;
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * WAVES), lds_bytes, st, table, count);
-  return hipGetLastError();
-}
-
 __global__ void k_write_insts(InstWrite w, BatchInst* __restrict__ table) {
   const int t = threadIdx.x;
   if (t < w.count) table[w.first + t] = w.v[t];
 }
 
-// per-iteration counters of every instance: zero-denominator events, non-positive kappa pairs
-__global__ void k_batched_reset(const BatchInst* __restrict__ table, int count) {
+// per-iteration counters of every instance (zero-denominator events, non-positive kappa pairs) and
+// the persistent pass's work counter
+__global__ void k_batched_reset(const BatchInst* __restrict__ table, int count, BatchWork* __restrict__ work,
+                                int nclasses) {
   for (int k = threadIdx.x; k < count; k += blockDim.x) {
     table[k].cnt[C_ZERO_DEN] = 0ull;
     table[k].cnt[C_KAPPA_BAD] = 0ull;
   }
+  for (int c = threadIdx.x; c < nclasses; c += blockDim.x) work[c].next = 0u;
 }
 
 // rho = acc 2^-32 / s of every instance (blockIdx.y: table entry)
@@ -815,34 +853,53 @@ hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_batched_reset(const BatchInst* table, int count, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batched_reset, dim3(1), dim3(256), 0, st, table, count);
+hipError_t launch_batched_reset(const BatchInst* table, int count, BatchWork* work, int nclasses, hipStream_t st) {
+  hipLaunchKernelGGL(k_batched_reset, dim3(1), dim3(256), 0, st, table, count, work, nclasses);
   return hipGetLastError();
 }
 
-hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxlen, int waves, int acc32,
-                                     size_t lds_bytes, int64_t grid, hipStream_t st) {
+hipError_t launch_batched_work(BatchInst* table, int count, BatchWork* work, int nclasses, hipStream_t st) {
+  hipLaunchKernelGGL(k_batched_work, dim3(1), dim3(64), 0, st, table, count, work, nclasses);
+  return hipGetLastError();
+}
+
+namespace {
+template <int MAXLEN, int WAVES>
+hipError_t launch_persistent_t(const BatchInst* table, int count, BatchWork* work, size_t lds_bytes, int grid,
+                               hipStream_t st) {
+  // the dynamic LDS limit is raised beforehand (set_persistent_lds), outside any stream capture
+  auto kern = k_event_pass_persistent<MAXLEN, WAVES>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * WAVES), lds_bytes, st, table, count, work);
+  return hipGetLastError();
+}
+
+const void* persistent_kernel(int maxlen, int waves) {
+  switch (maxlen * 100 + waves) {
+    case 1608: return (const void*)k_event_pass_persistent<16, 8>;
+    case 3208: return (const void*)k_event_pass_persistent<32, 8>;
+    case 1616: return (const void*)k_event_pass_persistent<16, 16>;
+    case 3216: return (const void*)k_event_pass_persistent<32, 16>;
+    default: return nullptr;
+  }
+}
+}  // namespace
+
+hipError_t launch_event_pass_persistent(const BatchInst* table, int count, BatchWork* work, int maxlen, int waves,
+                                        size_t lds_bytes, int grid, hipStream_t st) {
   if (count <= 0 || grid <= 0) return hipSuccess;
-  switch (maxlen * 100 + waves + (acc32 ? 10000 : 0)) {
-    case 1608: return launch_batched<16, 8, false>(table, count, lds_bytes, grid, st);
-    case 3208: return launch_batched<32, 8, false>(table, count, lds_bytes, grid, st);
-    case 4808: return launch_batched<48, 8, false>(table, count, lds_bytes, grid, st);
-    case 6408: return launch_batched<64, 8, false>(table, count, lds_bytes, grid, st);
-    case 1616: return launch_batched<16, 16, false>(table, count, lds_bytes, grid, st);
-    case 3216: return launch_batched<32, 16, false>(table, count, lds_bytes, grid, st);
-    case 4816: return launch_batched<48, 16, false>(table, count, lds_bytes, grid, st);
-    case 6416: return launch_batched<64, 16, false>(table, count, lds_bytes, grid, st);
-    case 11608: return launch_batched<16, 8, true>(table, count, lds_bytes, grid, st);
-    case 13208: return launch_batched<32, 8, true>(table, count, lds_bytes, grid, st);
-    case 14808: return launch_batched<48, 8, true>(table, count, lds_bytes, grid, st);
-    case 16408: return launch_batched<64, 8, true>(table, count, lds_bytes, grid, st);
-    case 11616: return launch_batched<16, 16, true>(table, count, lds_bytes, grid, st);
-    case 13216: return launch_batched<32, 16, true>(table, count, lds_bytes, grid, st);
-    case 14816: return launch_batched<48, 16, true>(table, count, lds_bytes, grid, st);
-    case 16416: return launch_batched<64, 16, true>(table, count, lds_bytes, grid, st);
+  switch (maxlen * 100 + waves) {
+    case 1608: return launch_persistent_t<16, 8>(table, count, work, lds_bytes, grid, st);
+    case 3208: return launch_persistent_t<32, 8>(table, count, work, lds_bytes, grid, st);
+    case 1616: return launch_persistent_t<16, 16>(table, count, work, lds_bytes, grid, st);
+    case 3216: return launch_persistent_t<32, 16>(table, count, work, lds_bytes, grid, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t set_persistent_lds(int maxlen, int waves, size_t lds_bytes) {
+  const void* k = persistent_kernel(maxlen, waves);
+  if (!k) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
 hipError_t launch_update_batched(const BatchInst* table, int count, int64_t max_npix, hipStream_t st) {

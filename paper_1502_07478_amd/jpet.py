@@ -101,6 +101,9 @@ def _lib():
         L.jpet_mlem_batched_workspace_size.argtypes = [ip, i32, ctypes.POINTER(sz)]
         L.jpet_mlem_batched_prepare.argtypes = [ip, i32, vp, sz, vp]
         L.jpet_mlem_batched_iterate.argtypes = [ip, i32, i32, vp, sz, u32, sp, vp]
+        L.jpet_mlem_batched_graph_create.argtypes = [ip, i32, i32, vp, sz, u32, vp, ctypes.POINTER(vp)]
+        L.jpet_mlem_batched_graph_launch.argtypes = [vp, vp]
+        L.jpet_mlem_batched_graph_destroy.argtypes = [vp]
         L.jpet_mlem_launch_info.argtypes = [gp, i64, ctypes.POINTER(LaunchInfo)]
         L.jpet_mlem_plan_candidates.argtypes = [gp, i32, ctypes.POINTER(ctypes.c_double), i64,
                                                 ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), i32,
@@ -398,12 +401,13 @@ class ChunkedMLEM:
 
 
 class BatchedMLEM:
-    """Many independent reconstructions advanced together (jpet_mlem_batched_*): one event-pass
-    launch per iteration for the whole batch.
+    """Many independent reconstructions advanced together (jpet_mlem_batched_*): one persistent
+    event-pass launch per iteration for the whole batch.
 
     instances: list of (geometry, events float32 [n, 3], sensitivity or None, rho float32 [n_y, n_z]),
-    all CUDA tensors on one device; each rho is updated in place by iterate().  The events are
-    prepared once, here.
+    all CUDA tensors on one device; each rho is updated in place by iterate() and run().  The events
+    are prepared once, here.  run(n) launches a HIP graph of n iterations, captured on its first
+    use for that n (jpet_mlem_batched_graph_*); iterate(n) enqueues the iterations one by one.
     """
 
     def __init__(self, instances, stream=None):
@@ -425,18 +429,48 @@ class BatchedMLEM:
         self.ws = torch.empty(max(int(b.value), 256), dtype=torch.uint8, device=dev)
         _check(_lib().jpet_mlem_batched_prepare(arr, self.count, _ptr(self.ws), self.ws.numel(), _stream(stream)),
                "jpet_mlem_batched_prepare")
+        self._graphs = {}
+        self._table_of = None
 
     def iterate(self, n_iter: int, want_stats: bool = False, stream=None):
         """n_iter iterations of every instance; per-instance stats dicts when want_stats."""
         st = (Stats * max(self.count, 1))() if want_stats else None
         _check(_lib().jpet_mlem_batched_iterate(self.arr, self.count, int(n_iter), _ptr(self.ws), self.ws.numel(),
                                                 JPET_WS_PREPARED, st, _stream(stream)), "jpet_mlem_batched_iterate")
+        self._table_of = None  # the eager call rewrote the instance table
         return [st[k].as_dict() for k in range(self.count)] if want_stats else None
 
-    def run(self, n_iter: int = 10, want_stats: bool = False, stream=None):
+    def graph(self, n_iter: int, stream=None):
+        """The captured graph of n_iter iterations (created on first use)."""
+        if getattr(self, "_table_of", None) != n_iter or n_iter not in self._graphs:
+            # a graph relies on the table its creation wrote: recreate after eager calls
+            self.close_graphs()
+            h = ctypes.c_void_p(None)
+            _check(_lib().jpet_mlem_batched_graph_create(self.arr, self.count, int(n_iter), _ptr(self.ws),
+                                                         self.ws.numel(), JPET_WS_PREPARED, _stream(stream),
+                                                         ctypes.byref(h)), "jpet_mlem_batched_graph_create")
+            self._graphs[n_iter] = h
+            self._table_of = n_iter
+        return self._graphs[n_iter]
+
+    def run(self, n_iter: int = 10, stream=None):
         """The whole reconstruction of every instance: n_iter iterations (the batched workload
-        runs 10); the images are updated in place."""
-        return self.iterate(n_iter, want_stats=want_stats, stream=stream)
+        runs 10) as one graph launch; the images are updated in place."""
+        h = self.graph(n_iter, stream)
+        _check(_lib().jpet_mlem_batched_graph_launch(h, _stream(stream)), "jpet_mlem_batched_graph_launch")
+
+    def close_graphs(self):
+        for h in self._graphs.values():
+            _lib().jpet_mlem_batched_graph_destroy(h)
+        self._graphs = {}
+
+    def __del__(self):
+        try:
+            if self._graphs:
+                torch.cuda.synchronize()
+            self.close_graphs()
+        except Exception:
+            pass
 
 
 @dataclass

@@ -119,3 +119,30 @@ def test_batch64_full_size():
     for k, (rho_o, sto) in zip(small, ref):
         assert stats[k]["n_pairs"] == sto["n_pairs"]
         assert rel_l2(images[k].cpu().numpy(), rho_o) <= 1e-4, base[k].name
+
+
+def test_batched_graph_replays_match_eager_iterations():
+    """The captured graph of a batch (reset, persistent pass and update per iteration) against the
+    same iterations enqueued eagerly on a second copy of the batch: three replays, with unrelated
+    eager GPU work and synchronisations between them, each checked against the eager images."""
+    base = batch_instances()[:8]
+    counts = [3000, 0, 2500, 1, 4000, 1700, 3500, 2222]
+    ws_list = [(w, w.events(n)) for w, n in zip(base, counts)]
+    t = get_workload("tiny")
+    ws_list.append((t.replace(n_events=5000), t.events(5000)))
+    inst_a, imgs_a = _setup(ws_list, True)
+    inst_b, imgs_b = _setup(ws_list, True)
+    ba, bb = jpet.BatchedMLEM(inst_a), jpet.BatchedMLEM(inst_b)
+    for rep in range(3):
+        ba.run(2)
+        bb.iterate(2)
+        torch.cuda.synchronize()
+        x = torch.randn(1 << 20, device=DEV)
+        float(x.sum())
+        for k, (a, b) in enumerate(zip(imgs_a, imgs_b)):
+            assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-6, (rep, k)
+    # and against the oracle after all six iterations
+    ref = _pool_map(_oracle_run, [(w.geometry(), ev, 6, True) for w, ev in ws_list])
+    for k, (rho_o, sto) in enumerate(ref):
+        if sto["n_valid"]:
+            assert rel_l2(imgs_a[k].cpu().numpy(), rho_o) <= 6e-4, k
