@@ -320,6 +320,20 @@ int jpet_mlem_launch_info(const jpet_geometry* g, int64_t n_events, jpet_launch_
 int jpet_mlem_plan_candidates(const jpet_geometry* g, int32_t pass, const double* sigma_mask, int64_t n_events,
                               int32_t* codes, double* model_cost, int32_t cap, int32_t* count);
 
+/* Autotuning support: the time of the MLEM event pass under each of the named plans, measured
+ * on the caller's events and image (an autotuner lists plans with jpet_mlem_plan_candidates, times
+ * them here and names the fastest in jpet_geometry.plan).  For each code: the events are prepared
+ * with that plan into the workspace, one pass runs untimed, then reps passes are timed with HIP
+ * events on stream; ms_out[k] (host) receives the mean milliseconds per pass, or -1 when the plan
+ * does not fit.  The passes' back-projections go to the workspace and are discarded; rho is only
+ * read.  Synchronises the stream.  The workspace must hold jpet_mlem_tune_workspace_size bytes
+ * (the largest of the codes' workspaces); g->plan is ignored.
+ *   events: device float [n][3]; rho: device float [n_y*n_z]; codes: host int32 [ncodes]; reps >= 1 */
+int jpet_mlem_tune_workspace_size(const jpet_geometry* g, int64_t n_events, const int32_t* codes, int32_t ncodes,
+                                  size_t* bytes);
+int jpet_mlem_tune(const jpet_geometry* g, const float* events, int64_t n, const float* rho, const int32_t* codes,
+                   int32_t ncodes, int32_t reps, void* ws, size_t ws_bytes, double* ms_out, void* stream);
+
 /* Kernel timing.  While enabled (enable != 0), every launch of the MLEM event pass made by
  * jpet_mlem_iterate and jpet_mlem_backproject, and every iteration's group of event-pass launches
  * made by jpet_mlem_batched_iterate, is bracketed by a pair of HIP events recorded on the caller's stream (the

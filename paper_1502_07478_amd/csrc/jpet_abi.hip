@@ -240,7 +240,7 @@ void plan_candidates(const jpet_geometry* g, double msz, double mdl, int64_t n, 
   // the second term being the staging of the image region and the flush of its accumulators
   // (about 1.6 pair evaluations per region pixel); items are the events over the events per item
   // plus, at most, one partial item per bin.
-  // (the log-likelihood pass, with its derivative terms, keeps 5 / 4 / 4 / 4).  Rows longer than
+  // (the log-likelihood pass, with its derivative terms, keeps 6 / 4 / 4 / 4).  Rows longer than
   // a cache of 16 or 32 may also be split into two segments, one thread each (x 1.3: the second
   // row setups, the shorter segments and the lanes they leave idle; a prior, not a measurement,
   // that keeps whole rows the model's choice wherever they fit and leaves split plans to timing).
@@ -249,15 +249,14 @@ void plan_candidates(const jpet_geometry* g, double msz, double mdl, int64_t n, 
     if (cache > 0) {
       maxlen = cache == 1 ? 16 : 32;
       if (!(maxrow > maxlen && maxrow <= 2 * maxlen)) continue;  // not needed, or too long to split in two
-      if (loglik) continue;                                      // the log-likelihood pass keeps whole rows
       segs = 2;
     }
-    const int simd_waves = loglik ? (maxlen <= 16 ? 5 : 4) : maxlen <= 16 ? 8 : maxlen <= 32 ? 6 : maxlen <= 48 ? 5 : 4;
+    const int simd_waves = loglik ? (maxlen <= 16 ? 6 : 4) : maxlen <= 16 ? 8 : maxlen <= 32 ? 6 : maxlen <= 48 ? 5 : 4;
     // LDS per CU, the passes' static LDS (per-event denominators; the log-likelihood pass also its
     // derivative sums), and the allocation granule: measured on gfx950, three workgroups of 51,984
     // bytes each run on one CU but three of 54,032 bytes do not (the pass then runs 27% slower), so
     // a workgroup's LDS is counted in whole 2 KB granules.
-    const size_t kLdsPerCU = 160 * 1024, kStatic = loglik ? 2 * 1024 : 1024, kGranule = 2048;
+    const size_t kLdsPerCU = 160 * 1024, kStatic = loglik ? 3 * 1024 : 1024, kGranule = 2048;
     const double pairs_per_event = 3.14159265358979323846 * hy_px * (3.0 * msz / sqrt(2.0) / pix);
     const double nn = (double)(n > 0 ? n : 1);
     for (int waves : {8, 16}) {
@@ -774,6 +773,75 @@ int jpet_mlem_denominators(const jpet_geometry* g, const float* events, int64_t 
   if (rc) return rc;
   if ((e = launch_fill_u64(w.acc, npix_of(g), st)) != hipSuccess) return hip_fail(e);
   if (stats) return read_stats(w, n, stats, st);
+  return JPET_OK;
+}
+
+int jpet_mlem_tune_workspace_size(const jpet_geometry* g, int64_t n_events, const int32_t* codes, int32_t ncodes,
+                                  size_t* bytes) {
+  int rc = check_geometry(g);
+  if (rc) return rc;
+  if (!bytes || n_events < 0 || n_events > kMaxEvents || ncodes < 0 || (ncodes > 0 && !codes)) return JPET_EINVAL;
+  size_t most = 0;
+  for (int32_t k = 0; k < ncodes; ++k) {
+    if (!plan_code_valid(codes[k])) return JPET_EINVAL;
+    jpet_geometry gk = *g;
+    gk.plan = codes[k];
+    const Plan p = make_plan(&gk, gk.sigma_z, gk.sigma_dl, n_events);
+    if (p.invalid) continue;  // timed as not fitting
+    const size_t b = workspace_layout(p, n_events, npix_of(g), nullptr, nullptr);
+    if (b > most) most = b;
+  }
+  *bytes = most;
+  return JPET_OK;
+}
+
+int jpet_mlem_tune(const jpet_geometry* g, const float* events, int64_t n, const float* rho, const int32_t* codes,
+                   int32_t ncodes, int32_t reps, void* ws, size_t ws_bytes, double* ms_out, void* stream) {
+  int rc = check_geometry(g);
+  if (rc) return rc;
+  if (n < 0 || n > kMaxEvents || (n > 0 && !events) || !rho || ncodes < 0 || (ncodes > 0 && (!codes || !ms_out)) ||
+      reps < 1)
+    return JPET_EINVAL;
+  for (int32_t k = 0; k < ncodes; ++k)
+    if (!plan_code_valid(codes[k])) return JPET_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e);
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e);
+  }
+  struct Guard {
+    hipEvent_t a, b;
+    ~Guard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  for (int32_t k = 0; k < ncodes; ++k) {
+    ms_out[k] = -1.0;  // does not fit
+    jpet_geometry gk = *g;
+    gk.plan = codes[k];
+    const Plan p = make_plan(&gk, gk.sigma_z, gk.sigma_dl, n);
+    if (p.invalid) continue;
+    Workspace w;
+    rc = carve(p, &gk, n, ws, ws_bytes, &w);
+    if (rc) return rc;
+    const Geo geo = make_geo(&gk, gk.sigma_z, gk.sigma_dl);
+    if ((rc = do_prepare(geo, p, events, n, w, st))) return rc;
+    if ((e = launch_fill_u64(w.acc, npix_of(g), st)) != hipSuccess) return hip_fail(e);
+    // one pass untimed (first-launch costs), then reps passes; rho is only read
+    if ((e = launch_event_pass(geo, p, n, w, rho, st)) != hipSuccess) return hip_fail(e);
+    if ((e = hipEventRecord(e0, st)) != hipSuccess) return hip_fail(e);
+    for (int32_t r = 0; r < reps; ++r)
+      if ((e = launch_event_pass(geo, p, n, w, rho, st)) != hipSuccess) return hip_fail(e);
+    if ((e = hipEventRecord(e1, st)) != hipSuccess) return hip_fail(e);
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e);
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return hip_fail(e);
+    ms_out[k] = (double)ms / reps;
+  }
   return JPET_OK;
 }
 

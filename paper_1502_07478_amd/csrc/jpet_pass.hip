@@ -144,6 +144,7 @@ struct RowD {
 struct GradShared {
   float Du[3][kMaxBatch];  // per-event sums of rho P' dlogP/du, buffered like D
   float Dw[3][kMaxBatch];
+  double sum[3][kMaxBatch];  // per batch slot: sums of log D', Du / D', Dw / D' over the item's events
 };
 
 template <int MAXLEN, bool GUARD>
@@ -304,12 +305,10 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       for (int b = 0; b < 3; ++b) {
         gsh->Du[b][tid] = 0.0f;
         gsh->Dw[b][tid] = 0.0f;
+        gsh->sum[b][tid] = 0.0;
       }
     }
   }
-  // log-likelihood mode: per-thread double sums of log D', Du / D', Dw / D' (events tid < 32)
-  double s_log = 0.0, s_du = 0.0, s_dw = 0.0;
-  int pidx = -1;  // input index of event tid of the previous batch
   const float iu = (float)(1.0 / g.u), iw = (float)(1.0 / g.w);
   const float cuf = (float)g.cu, cwf = (float)g.cw;  // prefactor terms of d log P / du, dw
   const float irs = 1.1774100225154747f;     // 1 / sqrt(log2(e) / 2)
@@ -357,16 +356,18 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
         const float invD = n2 > 0 ? (float)(1.0 / Dd) : 0.0f;
         pass2g<MAXLEN>(m, invD, pbase, pitch, n2, pwn, pwl, reinterpret_cast<double*>(acc_s));
         const int nbp = min(p.ev_per_batch, it.count - (bi - 1) * p.ev_per_batch);
-        if (tid < nbp) {
+        if (tid < nbp) {  // the batch slot's own sums (one thread each, in LDS, not registers)
           const double De = Dp[tid];
           if (De > 0.0) {
-            s_log += log(De);
-            s_du += (double)gsh->Du[(bi - 1) % 3][tid] / De;
-            s_dw += (double)gsh->Dw[(bi - 1) % 3][tid] / De;
+            gsh->sum[0][tid] += log(De);
+            gsh->sum[1][tid] += (double)gsh->Du[(bi - 1) % 3][tid] / De;
+            gsh->sum[2][tid] += (double)gsh->Dw[(bi - 1) % 3][tid] / De;
           } else {
             atomicAdd(&ps.zero, 1u);
           }
-          if (D_out) D_out[pidx] = (float)(De > 0.0 ? De * (double)Dnorm : 0.0);
+          if (D_out)
+            D_out[evs[it.start + (bi - 1) * p.ev_per_batch + tid].index] =
+                (float)(De > 0.0 ? De * (double)Dnorm : 0.0);
         }
       } else {
         // 2^32 / D overflows a float only for D < 1.3e-29; such wavefronts pre-scale m by 2^64
@@ -507,7 +508,6 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
           gsh->Dw[(bi + 1) % 3][tid] = 0.0f;
         }
       }
-      if constexpr (GRAD) pidx = tid < nb ? reinterpret_cast<const EvConst*>(evb)[tid].index : -1;
       plen = len;
       pbase = base;
       pe = e;
@@ -538,9 +538,11 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       }
     }
   }
-  if constexpr (GRAD) {  // events of the first wavefront only carry sums
+  if constexpr (GRAD) {  // the batch slots' sums, held by the first wavefront's lanes
     if (tid < WAVE) {
-      const double a = wave_sum_d(s_log), b = wave_sum_d(s_du), c = wave_sum_d(s_dw);
+      const bool slot = tid < kMaxBatch;
+      const double a = wave_sum_d(slot ? gsh->sum[0][tid] : 0.0), b = wave_sum_d(slot ? gsh->sum[1][tid] : 0.0),
+                   c = wave_sum_d(slot ? gsh->sum[2][tid] : 0.0);
       if (tid == 0) {
         unsafeAtomicAdd(&red[0], a);
         unsafeAtomicAdd(&red[1], b);
@@ -579,19 +581,23 @@ __global__ void __launch_bounds__(WAVES * 64, pass_waves_per_simd<MAXLEN>()) k_e
 
 // The log-likelihood pass on the binned layout (B: double image of sum P / D, zeroed by the
 // caller; red[0..2]: log D', Du / D', Dw / D' sums, zeroed by the caller).
+template <int MAXLEN>
+constexpr int loglik_waves_per_simd() {
+  return MAXLEN <= 16 ? 6 : 4;
+}
+
 template <int MAXLEN, int WAVES>
-__global__ void __launch_bounds__(WAVES * 64, MAXLEN <= 16 ? 5 : 4) k_loglik_tiled(Geo g, Plan p, const unsigned char* __restrict__ blocks,
-                                                                const BinItem* __restrict__ items,
-                                                                const float* __restrict__ rho, double* __restrict__ B,
-                                                                float* __restrict__ D_out, double* __restrict__ red,
-                                                                unsigned long long* __restrict__ cnt) {
+__global__ void __launch_bounds__(WAVES * 64, loglik_waves_per_simd<MAXLEN>())
+    k_loglik_tiled(Geo g, Plan p, const unsigned char* __restrict__ blocks, const BinItem* __restrict__ items,
+                   const float* __restrict__ rho, double* __restrict__ B, float* __restrict__ D_out,
+                   double* __restrict__ red, unsigned long long* __restrict__ cnt, const EventRec* __restrict__ evs) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ PassShared ps;
   __shared__ GradShared gsh;
   if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
   event_pass_item<MAXLEN, WAVES, true, false, 0>(g, p, blocks, items[blockIdx.x], rho,
                                                 reinterpret_cast<unsigned long long*>(B), cnt, smem, ps, &gsh, D_out,
-                                                red, nullptr);
+                                                red, evs);
 }
 
 // The same pass over many independent reconstructions, persistent: the grid is as many
@@ -826,7 +832,7 @@ hipError_t launch_loglik_t(const Geo& g, const Plan& p, const Workspace& ws, con
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)p.max_items), dim3(64 * p.waves), p.lds_bytes, st, g, p, ws.batches,
-                     ws.items, rho, ws.B, D_out, ws.red, ws.cnt);
+                     ws.items, rho, ws.B, D_out, ws.red, ws.cnt, ws.evs);
   return hipGetLastError();
 }
 

@@ -109,6 +109,9 @@ def _lib():
                                                 ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), i32,
                                                 ctypes.POINTER(i32)]
         L.jpet_mlem_denominators.argtypes = [gp, vp, i64, vp, vp, vp, sz, u32, sp, vp]
+        L.jpet_mlem_tune_workspace_size.argtypes = [gp, i64, ctypes.POINTER(i32), i32, ctypes.POINTER(sz)]
+        L.jpet_mlem_tune.argtypes = [gp, vp, i64, vp, ctypes.POINTER(i32), i32, i32, vp, sz,
+                                     ctypes.POINTER(ctypes.c_double), vp]
         L.jpet_profile_enable.argtypes = [ctypes.c_int]
         L.jpet_profile_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
         _L = L
@@ -410,9 +413,15 @@ class BatchedMLEM:
     use for that n (jpet_mlem_batched_graph_*); iterate(n) enqueues the iterations one by one.
     """
 
-    def __init__(self, instances, stream=None):
+    def __init__(self, instances, stream=None, tuned: bool = False):
+        """tuned: each instance takes its autotuned batched plan (paper_1502_07478_amd.tune; from its
+        plan cache, else timed now) instead of the cost model's choice."""
         self.keep = []
         arr = (Instance * max(len(instances), 1))()
+        if tuned:
+            from . import tune
+            instances = [(tune.tuned(g, ev, batched=True), ev, s, rho) for g, ev, s, rho in instances]
+        self.geometries = [g for g, _, _, _ in instances]
         for k, (g, ev, s, rho) in enumerate(instances):
             _events(ev)
             _need(rho, "rho", torch.float32, g.shape)

@@ -86,22 +86,21 @@ def prod():
     return w, ev_np, torch.from_numpy(ev_np).to(DEV)
 
 
-# The launch plan bench.py times at 400x400 with 10M events: 6 tan(theta~) bins of width 0.2,
-# 16-row tiles, 8-wavefront workgroups, 510-event workgroup items of 5-event batches and 32-bit
-# LDS accumulators in 2^-23 units.
-BENCH_PLAN = dict(binned=1, t_bins=6, t_bin_width=0.2, tile_rows=16, waves=8, events_per_batch=5,
-                  events_per_workgroup=510, accumulator_bits=32, accumulator_shift=23)
+def bench_geometry(w, ev):
+    """The geometry with the plan bench.py times: the autotuned one (tune.plan_for)."""
+    from paper_1502_07478_amd import tune
+    return tune.tuned(jpet.geometry(**w.geometry()), ev)
 
 
 def test_prod400_full_image_at_the_benchmarked_plan(prod, pool):
     """All 10M events, one step from rho^0: the whole image and every event's denominator as the
-    benchmarked pass computes them, against the oracle."""
+    benchmarked pass computes them (the plan bench.py takes), against the oracle."""
     w, ev_np, ev = prod
     kw = w.geometry()
-    g, go = jpet.geometry(**kw), oracle.geometry(**kw)
+    g, go = bench_geometry(w, ev), oracle.geometry(**kw)
     info = jpet.launch_info(g, len(ev_np))
-    for k, v in BENCH_PLAN.items():
-        assert info[k] == v, (k, info[k], v)
+    print(f"prod400 full: plan {info}", flush=True)
+    assert info["binned"] == 1 and info["plan"] == g.plan and info["events_per_workgroup"] >= 256
     s = jpet.sensitivity(g)
     so = oracle.sensitivity(go)
     rho0 = (s > 0).to(torch.float32)
@@ -127,11 +126,11 @@ def test_prod400_full_image_at_the_benchmarked_plan(prod, pool):
 
 def test_prod400_ten_step_trajectory_on_a_prefix_with_the_same_plan(prod, pool):
     """The first 600k events take the benchmarked plan (same bins, items, batches and accumulator
-    units); ten GPU steps in one call against ten oracle steps, checked after every step."""
+    units); ten GPU steps against ten oracle steps, checked after every step."""
     w, ev_np, ev = prod
     n = 600_000
     kw = w.geometry()
-    g, go = jpet.geometry(**kw), oracle.geometry(**kw)
+    g, go = bench_geometry(w, ev), oracle.geometry(**kw)
     full, pre = jpet.launch_info(g, len(ev_np)), jpet.launch_info(g, n)
     for k in full:
         if k != "max_workgroups":
@@ -156,7 +155,7 @@ def test_prod400_accumulator_units_32_against_64_bit(prod):
     rounding of terms below half a unit does not move low-activity pixels beyond the per-step
     bounds, also where the image is 1e-4 of its maximum and below."""
     w, ev_np, ev = prod
-    g = jpet.geometry(**w.geometry())
+    g = bench_geometry(w, ev)
     n = len(ev_np)
     assert jpet.launch_info(g, n)["accumulator_bits"] == 32
     code64 = next(code for code, _ in jpet.plan_candidates(g, n) if not code & 4)
