@@ -119,6 +119,10 @@ typedef struct jpet_stats {
  * to the accumulators in global memory; the result equals the planned pass's to rounding. */
 #define JPET_PASS_WAVE_PER_EVENT 2u
 #define JPET_PASS_THREAD_PER_EVENT 4u
+/* jpet_loglik_grad: the log-likelihood value alone (out3[1] and out3[2] are set to NaN and
+ * grad_rho must be NULL): one forward pass forming the denominators, with none of the
+ * back-projection or derivative work, e.g. for the function evaluations of a line search. */
+#define JPET_LOGLIK_VALUE_ONLY 8u
 
 /* Text for a status code (static storage, never NULL). */
 const char* jpet_strerror(int status);

@@ -349,9 +349,9 @@ Plan make_plan(const jpet_geometry* g, double msz, double mdl, int64_t n, bool l
 
 size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Workspace* out) {
   size_t off = 0;
-  char* b = (char*)base;
+  // offsets from base; a size query (base NULL) forms no pointers
   auto take = [&](size_t bytes) {
-    char* q = b + off;
+    char* q = base ? (char*)base + off : nullptr;
     off = align_up(off + bytes, 256);
     return q;
   };
@@ -863,7 +863,9 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
   int rc = check_geometry(g);
   if (rc) return rc;
   if (n < 0 || n > kMaxEvents || (n > 0 && !events) || !rho || !out3) return JPET_EINVAL;
-  if (flags & ~JPET_WS_PREPARED) return JPET_EINVAL;
+  if (flags & ~(JPET_WS_PREPARED | JPET_LOGLIK_VALUE_ONLY)) return JPET_EINVAL;
+  const bool value_only = (flags & JPET_LOGLIK_VALUE_ONLY) != 0;
+  if (value_only && grad_rho) return JPET_EINVAL;
   if (g->sigma_z_edge != 0.0) return JPET_ENOTSUP;  // defined for one sigma_z for all events
   double msz = g->sigma_z, mdl = g->sigma_dl;
   if (sigma_mask) {
@@ -887,7 +889,7 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
   }
   hipError_t e = launch_fill_u64(w.cnt + C_ZERO_DEN, 2, st);
   if (e != hipSuccess) return hip_fail(e);
-  e = launch_loglik(geo, p, n, w, rho, s, D_out, grad_rho, out3, st);
+  e = launch_loglik(geo, p, n, w, rho, s, D_out, grad_rho, out3, value_only, st);
   if (e != hipSuccess) return hip_fail(e);
   if (stats) {
     rc = read_stats(w, n, stats, st);

@@ -275,10 +275,13 @@ hipError_t launch_event_pass_persistent(const BatchInst* table, int count, Batch
 // raises a persistent pass's dynamic LDS limit (call before launching or capturing it)
 hipError_t set_persistent_lds(int maxlen, int waves, size_t lds_bytes);
 hipError_t launch_update_batched(const BatchInst* table, int count, int64_t max_npix, hipStream_t st);
+// value_only: l alone (out3[1], out3[2] are NaN, grad_rho must be null)
 hipError_t launch_loglik(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
-                         const float* s, float* D_out, float* grad_rho, double* out3, hipStream_t st);
-// the binned log-likelihood pass (B and red[0..2] zeroed by the caller)
+                         const float* s, float* D_out, float* grad_rho, double* out3, bool value_only,
+                         hipStream_t st);
+// the binned log-likelihood pass (B and red[0..2] zeroed by the caller); value_only: the per-event
+// log D' sums alone
 hipError_t launch_loglik_tiled(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
-                               float* D_out, hipStream_t st);
+                               float* D_out, bool value_only, hipStream_t st);
 
 }  // namespace jpet

@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(256) k_loglik_pass(Geo g, int64_t n, const Eve
 __global__ void __launch_bounds__(256) k_loglik_finish(Geo g, int nblocks, const double* __restrict__ red,
                                                        const float* __restrict__ rho, const float* __restrict__ s,
                                                        const unsigned long long* __restrict__ cnt,
-                                                       double* __restrict__ out3) {
+                                                       double* __restrict__ out3, int value_only) {
   __shared__ double sh[4][256];
   double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
   for (int q = threadIdx.x; q < nblocks; q += blockDim.x) {
@@ -226,8 +226,8 @@ __global__ void __launch_bounds__(256) k_loglik_finish(Geo g, int nblocks, const
     const double lognorm = log(g.cnorm / kPi);
     const double ll = sh[0][0] + (nvalid - nz) * lognorm - sh[3][0];
     out3[0] = nz > 0.0 ? -INFINITY : ll;
-    out3[1] = sh[1][0] * (-2.0 * g.u / g.sigma_z);
-    out3[2] = sh[2][0] * (-2.0 * g.w / g.sigma_dl);
+    out3[1] = value_only ? NAN : sh[1][0] * (-2.0 * g.u / g.sigma_z);
+    out3[2] = value_only ? NAN : sh[2][0] * (-2.0 * g.w / g.sigma_dl);
   }
 }
 
@@ -272,15 +272,16 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) {
 }
 
 hipError_t launch_loglik(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
-                         const float* s, float* D_out, float* grad_rho, double* out3, hipStream_t st) {
+                         const float* s, float* D_out, float* grad_rho, double* out3, bool value_only,
+                         hipStream_t st) {
   const int64_t npix = (int64_t)g.n_y * g.n_z;
   int nparts;
   if (p.tiled) {
-    // binned pass: B always accumulated (the pass has no B-free variant), three partial sums
-    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(npix, 256)), dim3(256), 0, st, ws.B, npix);
+    // binned pass: B accumulated (unless the value alone is asked for), three partial sums
+    if (!value_only) hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(npix, 256)), dim3(256), 0, st, ws.B, npix);
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, ws.red, (int64_t)3);
     if (D_out) hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256)), dim3(256), 0, st, D_out, n);
-    const hipError_t e = launch_loglik_tiled(g, p, n, ws, rho, D_out, st);
+    const hipError_t e = launch_loglik_tiled(g, p, n, ws, rho, D_out, value_only, st);
     if (e != hipSuccess) return e;
     nparts = 1;
   } else {
@@ -289,7 +290,8 @@ hipError_t launch_loglik(const Geo& g, const Plan& p, int64_t n, const Workspace
     hipLaunchKernelGGL(k_loglik_pass, dim3(nparts), dim3(256), 0, st, g, n, ws.ev, rho, grad_rho ? ws.B : nullptr,
                        D_out, ws.red, ws.cnt);
   }
-  hipLaunchKernelGGL(k_loglik_finish, dim3(1), dim3(256), 0, st, g, nparts, ws.red, rho, s, ws.cnt, out3);
+  hipLaunchKernelGGL(k_loglik_finish, dim3(1), dim3(256), 0, st, g, nparts, ws.red, rho, s, ws.cnt, out3,
+                     value_only ? 1 : 0);
   if (grad_rho) hipLaunchKernelGGL(k_grad_rho, dim3(grid_for(npix, 256)), dim3(256), 0, st, npix, ws.B, s, grad_rho);
   return hipGetLastError();
 }

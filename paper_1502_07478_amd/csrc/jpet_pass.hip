@@ -244,7 +244,9 @@ __device__ __forceinline__ void copy_consts(const unsigned char* __restrict__ sr
 // written at the event's input position (evs: the bin-sorted records).
 // GRAD = true: the log-likelihood pass (acc: double image B = sum P / D; per-event log D' and the
 // sigma-derivative sums into red[0..2]; D' times the kernel's constant factor into D_out).
-template <int MAXLEN, int WAVES, bool GRAD, bool ACC32, int PITCH>
+// VALUE (with GRAD): the log-likelihood value only: per-event log D' sums, no B, no
+// sigma-derivative terms (pass 1 as in the MLEM pass, no pass 2).
+template <int MAXLEN, int WAVES, bool GRAD, bool ACC32, int PITCH, bool VALUE = false>
 __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, const unsigned char* __restrict__ blocks,
                                                 const BinItem it, const float* __restrict__ rho,
                                                 unsigned long long* __restrict__ acc,
@@ -353,15 +355,19 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       const double Dd = plen > 0 ? Dp[pe] : 1.0;
       const int n2 = Dd > 0.0 ? plen : 0;
       if constexpr (GRAD) {
-        const float invD = n2 > 0 ? (float)(1.0 / Dd) : 0.0f;
-        pass2g<MAXLEN>(m, invD, pbase, pitch, n2, pwn, pwl, reinterpret_cast<double*>(acc_s));
+        if constexpr (!VALUE) {
+          const float invD = n2 > 0 ? (float)(1.0 / Dd) : 0.0f;
+          pass2g<MAXLEN>(m, invD, pbase, pitch, n2, pwn, pwl, reinterpret_cast<double*>(acc_s));
+        }
         const int nbp = min(p.ev_per_batch, it.count - (bi - 1) * p.ev_per_batch);
         if (tid < nbp) {  // the batch slot's own sums (one thread each, in LDS, not registers)
           const double De = Dp[tid];
           if (De > 0.0) {
             gsh->sum[0][tid] += log(De);
-            gsh->sum[1][tid] += (double)gsh->Du[(bi - 1) % 3][tid] / De;
-            gsh->sum[2][tid] += (double)gsh->Dw[(bi - 1) % 3][tid] / De;
+            if constexpr (!VALUE) {
+              gsh->sum[1][tid] += (double)gsh->Du[(bi - 1) % 3][tid] / De;
+              gsh->sum[2][tid] += (double)gsh->Dw[(bi - 1) % 3][tid] / De;
+            }
           } else {
             atomicAdd(&ps.zero, 1u);
           }
@@ -387,7 +393,6 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
     }
     if (bi < nbatch) {
       const int buf = bi & 1;
-      const int nb = min(p.ev_per_batch, it.count - bi * p.ev_per_batch);
       const unsigned char* evb = ev_lds + buf * cbytes;  // this batch's constants
       const int wl = (int)(wlw & 0x7fffffffu);
       const bool guard = (wlw >> kGuardBit) != 0u;  // wavefront-uniform
@@ -430,14 +435,16 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
           rk.qa = S2u * pixf * pixf;
           rk.qb = 2.0f * S2u * b10 * pixf;
           rk.qc = fmaf(S2u * b10, b10, c.Q3s * dy * dy);
-          rd.b10 = b10;
-          rd.Kzh0 = 0.5f * iu * fmaf(kb, b10, c.A1 * (R2 + Y * Y));
-          rd.dKzh = 0.5f * iu * kb * pixf;
-          rd.Gz0 = iu * gb * b10;
-          rd.dGz = iu * gb * pixf;
-          rd.Gl = iw * c.G1 * Y * dy;
-          rd.Klh = 0.5f * iw * Y * fmaf(c.A2, Y, c.A3 * dy);
-          rd.cw = cwf - 0.5f * iS * iw * c.Q3s * dy * dy;
+          if constexpr (!VALUE) {
+            rd.b10 = b10;
+            rd.Kzh0 = 0.5f * iu * fmaf(kb, b10, c.A1 * (R2 + Y * Y));
+            rd.dKzh = 0.5f * iu * kb * pixf;
+            rd.Gz0 = iu * gb * b10;
+            rd.dGz = iu * gb * pixf;
+            rd.Gl = iw * c.G1 * Y * dy;
+            rd.Klh = 0.5f * iw * Y * fmaf(c.A2, Y, c.A3 * dy);
+            rd.cw = cwf - 0.5f * iS * iw * c.Q3s * dy * dy;
+          }
         } else {
           // the row constants from the event's polynomials in the region row (see EvRow)
           const EvRow& c = reinterpret_cast<const EvRow*>(evb)[e];
@@ -459,7 +466,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       // kappa test only in wavefronts whose rows may need it (decided at prepare time)
       int nbad = 0;  // pixels of this thread's row with kappa <= 0 (P := 0)
       float D, Du = 0.0f, Dw = 0.0f;
-      if constexpr (GRAD) {
+      if constexpr (GRAD && !VALUE) {
         if (guard) {
           pass1g<MAXLEN, true>(rk, rd, qa, pixf, cuf, irs, rho_s, base, pitch, len, wn, wl, m, &nbad, D, Du, Dw);
         } else {
@@ -476,7 +483,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
 
       // per-event denominators
       double* Dc = ps.D[bi % 3];
-      if constexpr (GRAD) {
+      if constexpr (GRAD && !VALUE) {
         // segmented reduction over the wavefront's rows, one event at a time
         unsigned long long act = __ballot(len > 0);
         while (act) {
@@ -522,7 +529,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   }
 
   // add the region's accumulators to the global image (wavefronts take columns, lanes rows)
-  for (int cl = wave; cl < p.W; cl += WAVES) {
+  for (int cl = wave; cl < (VALUE ? 0 : p.W); cl += WAVES) {
     const int kc = kbase + cl;
     for (int rl = lane; rl < p.RY; rl += WAVE) {
       const unsigned long long a = (unsigned long long)acc_s[cl * pitch + rl] << flush_shift;
@@ -586,7 +593,7 @@ constexpr int loglik_waves_per_simd() {
   return MAXLEN <= 16 ? 6 : 4;
 }
 
-template <int MAXLEN, int WAVES>
+template <int MAXLEN, int WAVES, bool VALUE>
 __global__ void __launch_bounds__(WAVES * 64, loglik_waves_per_simd<MAXLEN>())
     k_loglik_tiled(Geo g, Plan p, const unsigned char* __restrict__ blocks, const BinItem* __restrict__ items,
                    const float* __restrict__ rho, double* __restrict__ B, float* __restrict__ D_out,
@@ -595,7 +602,7 @@ __global__ void __launch_bounds__(WAVES * 64, loglik_waves_per_simd<MAXLEN>())
   __shared__ PassShared ps;
   __shared__ GradShared gsh;
   if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
-  event_pass_item<MAXLEN, WAVES, true, false, 0>(g, p, blocks, items[blockIdx.x], rho,
+  event_pass_item<MAXLEN, WAVES, true, false, 0, VALUE>(g, p, blocks, items[blockIdx.x], rho,
                                                 reinterpret_cast<unsigned long long*>(B), cnt, smem, ps, &gsh, D_out,
                                                 red, evs);
 }
@@ -827,8 +834,8 @@ __global__ void k_update_batched(const BatchInst* __restrict__ table) {
 
 template <int MAXLEN, int WAVES>
 hipError_t launch_loglik_t(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, float* D_out,
-                           hipStream_t st) {
-  auto kern = k_loglik_tiled<MAXLEN, WAVES>;
+                           bool value_only, hipStream_t st) {
+  auto kern = value_only ? k_loglik_tiled<MAXLEN, WAVES, true> : k_loglik_tiled<MAXLEN, WAVES, false>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)p.max_items), dim3(64 * p.waves), p.lds_bytes, st, g, p, ws.batches,
@@ -839,17 +846,18 @@ hipError_t launch_loglik_t(const Geo& g, const Plan& p, const Workspace& ws, con
 }  // namespace
 
 hipError_t launch_loglik_tiled(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,
-                               float* D_out, hipStream_t st) {
+                               float* D_out, bool value_only, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  const bool v = value_only;
   switch (p.maxlen * 100 + p.waves) {
-    case 1608: return launch_loglik_t<16, 8>(g, p, ws, rho, D_out, st);
-    case 3208: return launch_loglik_t<32, 8>(g, p, ws, rho, D_out, st);
-    case 4808: return launch_loglik_t<48, 8>(g, p, ws, rho, D_out, st);
-    case 6408: return launch_loglik_t<64, 8>(g, p, ws, rho, D_out, st);
-    case 1616: return launch_loglik_t<16, 16>(g, p, ws, rho, D_out, st);
-    case 3216: return launch_loglik_t<32, 16>(g, p, ws, rho, D_out, st);
-    case 4816: return launch_loglik_t<48, 16>(g, p, ws, rho, D_out, st);
-    case 6416: return launch_loglik_t<64, 16>(g, p, ws, rho, D_out, st);
+    case 1608: return launch_loglik_t<16, 8>(g, p, ws, rho, D_out, v, st);
+    case 3208: return launch_loglik_t<32, 8>(g, p, ws, rho, D_out, v, st);
+    case 4808: return launch_loglik_t<48, 8>(g, p, ws, rho, D_out, v, st);
+    case 6408: return launch_loglik_t<64, 8>(g, p, ws, rho, D_out, v, st);
+    case 1616: return launch_loglik_t<16, 16>(g, p, ws, rho, D_out, v, st);
+    case 3216: return launch_loglik_t<32, 16>(g, p, ws, rho, D_out, v, st);
+    case 4816: return launch_loglik_t<48, 16>(g, p, ws, rho, D_out, v, st);
+    case 6416: return launch_loglik_t<64, 16>(g, p, ws, rho, D_out, v, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libjpet.so")
 JPET_OK, JPET_EINVAL, JPET_EDOMAIN, JPET_EWORKSPACE, JPET_EHIP, JPET_ENOTSUP = 0, -1, -2, -3, -4, -5
 JPET_WS_PREPARED = 1
 JPET_PASS_WAVE_PER_EVENT, JPET_PASS_THREAD_PER_EVENT = 2, 4
+JPET_LOGLIK_VALUE_ONLY = 8
 
 
 class JpetError(RuntimeError):
@@ -501,7 +502,9 @@ def loglik_workspace(g: Geometry, n_events: int, sigma_mask=None, device=None) -
 
 def loglik_grad(g: Geometry, events: torch.Tensor, rho: torch.Tensor, s: torch.Tensor | None = None,
                 sigma_mask=None, want_grad_rho: bool = True, want_D: bool = False, ws: torch.Tensor | None = None,
-                prepared: bool = False, want_stats: bool = False, stream=None) -> LogLik:
+                prepared: bool = False, want_stats: bool = False, stream=None, value_only: bool = False) -> LogLik:
+    """l, dl/dsigma and (want_grad_rho) dl/drho (jpet_loglik_grad); value_only: l alone (the
+    sigma entries of value are NaN, no grad_rho), one forward pass."""
     _events(events)
     _need(rho, "rho", torch.float32, g.shape)
     if s is not None:
@@ -511,12 +514,13 @@ def loglik_grad(g: Geometry, events: torch.Tensor, rho: torch.Tensor, s: torch.T
         ws = loglik_workspace(g, n, sigma_mask, rho.device)
         prepared = False
     out3 = torch.zeros(3, dtype=torch.float64, device=rho.device)
-    gr = torch.empty(g.shape, dtype=torch.float32, device=rho.device) if want_grad_rho else None
+    gr = torch.empty(g.shape, dtype=torch.float32, device=rho.device) if want_grad_rho and not value_only else None
     D = torch.empty(n, dtype=torch.float32, device=rho.device) if want_D else None
     sm = (ctypes.c_double * 2)(*sigma_mask) if sigma_mask is not None else None
     st = Stats() if want_stats else None
     rc = _lib().jpet_loglik_grad(ctypes.byref(g), sm, _ptr(events), n, _ptr(s), _ptr(rho), _ptr(out3), _ptr(gr),
-                                 _ptr(D), _ptr(ws), ws.numel(), JPET_WS_PREPARED if prepared else 0,
+                                 _ptr(D), _ptr(ws), ws.numel(),
+                                 (JPET_WS_PREPARED if prepared else 0) | (JPET_LOGLIK_VALUE_ONLY if value_only else 0),
                                  ctypes.byref(st) if st is not None else None, _stream(stream))
     # JPET_EDOMAIN after the pass means a valid event has D = 0 (l = -inf, reported through stats);
     # before it (a geometry or mask out of domain) nothing was written, which is an error
@@ -545,8 +549,10 @@ class JPetLogLik(torch.autograd.Function):
         sd = float(sigma_dl)
         gg = Geometry(g.R, g.L, sz, sd, g.gamma, g.pixel, g.n_y, g.n_z, g.kernel_variant, g.plan, g.sigma_z_edge)
         mask = (sz, sd) if sigma_mask is None else tuple(float(x) for x in sigma_mask)
+        # with no gradient asked for, the value alone (one forward pass)
+        need = any(ctx.needs_input_grad[:3])
         res = loglik_grad(gg, events, rho.detach().contiguous(), s=s, sigma_mask=mask,
-                          want_grad_rho=ctx.needs_input_grad[0])
+                          want_grad_rho=ctx.needs_input_grad[0], value_only=not need)
         ctx.save_for_backward(res.value, res.grad_rho if res.grad_rho is not None else torch.empty(0))
         ctx.sig = [(x.dtype, x.device) if isinstance(x, torch.Tensor) else None for x in (sigma_z, sigma_dl)]
         return res.value[0].clone()

@@ -651,3 +651,26 @@ def test_loglik_out_of_domain_mask_with_a_caller_workspace_raises(tiny):
         jpet.loglik_grad(g, ev, rho, s=s, ws=ws, sigma_mask=(0.0, 63.0))
     with pytest.raises(jpet.JpetError):
         jpet.loglik_grad(g, ev, rho, s=s, ws=ws, sigma_mask=(0.0, 63.0), want_stats=True)
+
+
+def test_loglik_value_only_matches_oracle_and_full_call(tiny):
+    """JPET_LOGLIK_VALUE_ONLY: the log-likelihood from one forward pass equals the oracle's and the
+    full call's; its sigma entries are NaN, its denominators the oracle's."""
+    w, ev_np, ev = tiny
+    g, go = geoms(w)
+    so = oracle.sensitivity(go)
+    rho_o, _ = oracle.mlem(go, ev_np, oracle.initial_image(so), 2, s=so)
+    rho = torch.from_numpy(rho_o.astype(np.float32)).to(DEV)
+    s = jpet.sensitivity(g)
+    v = jpet.loglik_grad(g, ev, rho, s=s, want_D=True, value_only=True, want_stats=True)
+    full = jpet.loglik_grad(g, ev, rho, s=s, want_grad_rho=False)
+    l, dz, dd, gr, sto, D = oracle.loglik_grad(go, ev_np, rho.double().cpu().numpy(), s=so, return_D=True)
+    vv = v.value.cpu().numpy()
+    assert vv[0] == pytest.approx(l, rel=1e-6)
+    assert vv[0] == pytest.approx(float(full.value[0]), rel=1e-6)
+    assert np.isnan(vv[1]) and np.isnan(vv[2]) and v.grad_rho is None
+    np.testing.assert_allclose(v.D.double().cpu().numpy(), D, rtol=2e-5, atol=1e-30)
+    assert v.stats["n_pairs"] == sto["n_pairs"]
+    # autograd with nothing to differentiate takes the same path
+    lv = jpet.loglik(rho, w.sigma_z, w.sigma_dl, ev, g, s)
+    assert float(lv) == pytest.approx(l, rel=1e-6)
