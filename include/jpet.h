@@ -235,14 +235,15 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
                      size_t ws_bytes, uint32_t flags, jpet_stats* stats, void* stream);
 
 /* Batched reconstruction: many independent list-mode MLEM problems (each with its own geometry,
- * resolution, event list, sensitivity and image) advanced together.  Per iteration one persistent
- * event-pass launch serves every instance that fits the binned pass: its workgroups, as many as
- * stay resident, pull (instance, workgroup item) work from a counter, the instances' items in
- * order of decreasing size, until all are done; instances that fit only the generic pass get their
- * own launches.  All binned instances use one kernel configuration (see jpet_geometry.plan: codes
- * named for a batch must share 8-wavefront workgroups, 32-bit accumulators, the residency per CU
- * and a register cache of at most 32 pixels, else JPET_EDOMAIN).  Each instance's result is that of
- * jpet_mlem_iterate on it alone with the same plan, to FP32 rounding of the denominators.
+ * resolution, event list, sensitivity and image) advanced together (one MLEM iteration of each is
+ * the Sec. 4 listing with Eq. 3).  Instances that fit the binned pass are grouped into classes by
+ * kernel configuration (wavefronts per workgroup, workgroups per CU, region row pitch); per
+ * iteration each class is one launch with one workgroup per workgroup item of its instances, the
+ * items in order of decreasing size.  Instances that fit only the generic pass get their own
+ * launches.  A plan named in an instance's jpet_geometry.plan must be one the batched pass can run:
+ * 32-bit accumulators and a register cache of at most 32 pixels (else JPET_EDOMAIN); plan 0 takes
+ * the cost model's cheapest such plan.  Each instance's result is that of jpet_mlem_iterate on it
+ * alone with the same plan, to FP32 rounding of the denominators.
  * Host struct; pointers as for jpet_mlem_iterate. */
 typedef struct jpet_instance {
   jpet_geometry g;
@@ -266,7 +267,7 @@ int jpet_mlem_batched_prepare(const jpet_instance* inst, int32_t count, void* ws
 int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t n_iter, void* ws, size_t ws_bytes,
                               uint32_t flags, jpet_stats* stats, void* stream);
 
-/* The same n_iter iterations captured once into a HIP graph (a reset, the persistent pass, any
+/* The same n_iter iterations captured once into a HIP graph (a reset, the batched passes, any
  * generic passes and the update per iteration, all kernels), for repeated launches with no host
  * work.  Creating the graph prepares the instances (unless JPET_WS_PREPARED) and writes the batch's
  * instance table and work list into the workspace on stream, in stream order, before capturing;

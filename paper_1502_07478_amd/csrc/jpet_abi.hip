@@ -379,26 +379,28 @@ size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Work
   return off;
 }
 
-// Layout of a batched workspace: the instance table, one work counter per class, then one
-// ordinary workspace per instance.  Every instance that fits the binned pass takes the plan its
-// geometry names or the cost model's cheapest plan with 32-bit accumulators and a register cache
-// of at most 32 pixels (longer rows are split into two segments).  Instances whose plans share the
-// wavefronts per workgroup and the workgroups resident per CU form a class, served by one
-// persistent launch per iteration with the class's largest LDS region and register cache; a batch
-// of like instances is one class.  Within a class the table lists the instances heaviest workgroup
+// Layout of a batched workspace: the instance table, one work list per class, then one ordinary
+// workspace per instance.  Every instance that fits the binned pass takes the plan its geometry
+// names or the cost model's cheapest plan with 32-bit accumulators and a register cache of at most
+// 32 pixels (longer rows are split into two segments).  Instances whose plans share the wavefronts
+// per workgroup, the workgroups resident per CU and the region's row pitch (64, 128, 256 or any
+// other) form a class, served by one batched launch per iteration with the class's largest LDS
+// region and register cache; a batch of like instances is one class.  Within a class the table lists the instances heaviest workgroup
 // item first, so that the longest items are pulled earliest.  Instances that fit only the generic
 // pass follow the classes, with their own launches.
 struct BatchClass {
   int first = 0, count = 0;  // table positions
   int maxlen = 0, waves = 0, wgs = 0;
+  int pitch = 0;             // region row pitch the class is compiled for (0: a runtime value)
   size_t lds = 0;
+  int64_t grid = 0;          // upper bound of the class's workgroup items (sum of max_items)
 };
 
 struct BatchLayout {
   std::vector<Plan> plan;       // per instance
   std::vector<size_t> off;      // per instance: byte offset of its workspace
   std::vector<int> order;       // table position -> instance
-  std::vector<BatchClass> cls;  // the persistent launches
+  std::vector<BatchClass> cls;  // the batched launches
   int64_t max_npix = 0;
   size_t work_off = 0;          // BatchWork[cls.size()]
   size_t total = 0;
@@ -438,7 +440,7 @@ BatchLayout batch_layout(const jpet_instance* inst, int count) {
     }
     L.plan[k] = p;
     if (p.tiled) {
-      key[k] = p.waves * 8 + p.wgs;
+      key[k] = (batched_pitch_class(p.pitch) * 32 + p.waves) * 8 + p.wgs;
       // pixels of a typical ellipse (App. B half sizes at theta = 0) times events per workgroup
       work[k] = (1.5 * g.sigma_dl / g.pixel) * (3.0 * g.sigma_z / sqrt(2.0) / g.pixel) * p.ev_per_wg;
     }
@@ -460,10 +462,12 @@ BatchLayout batch_layout(const jpet_instance* inst, int count) {
       c.first = t;
       c.waves = p.waves;
       c.wgs = p.wgs;
+      c.pitch = batched_pitch_class(p.pitch);
       L.cls.push_back(c);
     }
     BatchClass& c = L.cls.back();
     ++c.count;
+    c.grid += p.max_items;
     c.maxlen = p.maxlen > c.maxlen ? p.maxlen : c.maxlen;
     if (p.lds_bytes > c.lds) c.lds = p.lds_bytes;
   }
@@ -980,32 +984,23 @@ static int batched_setup(const jpet_instance* inst, int32_t count, const BatchLa
   return JPET_OK;
 }
 
-// The device's compute units (the persistent launches' grids are a multiple of them).
-static int device_cus(int* cus) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return hip_fail(e);
-  return JPET_OK;
-}
-
-// n_iter iterations of a set-up batch: per iteration the counters' reset, one persistent pass per
+// n_iter iterations of a set-up batch: per iteration the counters' reset, one batched pass per
 // class over its instances' items, the generic instances' passes and the pixel update of all.
 static int batched_iterations(const jpet_instance* inst, int32_t count, int32_t n_iter, const BatchLayout& L,
-                              const std::vector<Workspace>& w, const std::vector<Geo>& geo, void* ws, int cus,
-                              bool timing, hipStream_t st) {
+                              const std::vector<Workspace>& w, const std::vector<Geo>& geo, void* ws, bool timing,
+                              hipStream_t st) {
   BatchInst* table = reinterpret_cast<BatchInst*>(ws);
   BatchWork* work = reinterpret_cast<BatchWork*>((char*)ws + L.work_off);
   hipError_t e;
   for (int it = 0; it < n_iter; ++it) {
-    if ((e = launch_batched_reset(table, count, work, (int)L.cls.size(), st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_batched_reset(table, count, st)) != hipSuccess) return hip_fail(e);
     if (!L.cls.empty()) {
       auto pass = [&] {
         hipError_t r = hipSuccess;
         for (size_t c = 0; c < L.cls.size() && r == hipSuccess; ++c) {
           const BatchClass& C = L.cls[c];
-          r = launch_event_pass_persistent(table + C.first, C.count, work + c, C.maxlen, C.waves, C.lds, cus * C.wgs,
-                                           st);
+          r = launch_event_pass_batched(table + C.first, C.count, work + c, C.maxlen, C.waves, C.pitch, C.lds, C.grid,
+                                        st);
         }
         return r;
       };
@@ -1029,8 +1024,7 @@ static int batched_iterations(const jpet_instance* inst, int32_t count, int32_t 
 // A batch, validated and carved, with its geometries; prepared (unless flagged as prepared) and set
 // up for iterating on stream st.
 static int batched_begin(const jpet_instance* inst, int32_t count, void* ws, size_t ws_bytes, uint32_t flags,
-                         hipStream_t st, BatchLayout* L, std::vector<Workspace>* w, std::vector<Geo>* geo,
-                         int* cus) {
+                         hipStream_t st, BatchLayout* L, std::vector<Workspace>* w, std::vector<Geo>* geo) {
   int rc = batched_carve(inst, count, ws, ws_bytes, L, w);
   if (rc) return rc;
   geo->resize(count);
@@ -1041,9 +1035,13 @@ static int batched_begin(const jpet_instance* inst, int32_t count, void* ws, siz
       if (rc) return rc;
     }
   }
-  if ((rc = device_cus(cus))) return rc;
-  for (const BatchClass& C : L->cls) {
-    const hipError_t e = set_persistent_lds(C.maxlen, C.waves, C.lds);
+  // classes compiled alike share one kernel, whose LDS limit is their largest region
+  for (size_t c = 0; c < L->cls.size(); ++c) {
+    const BatchClass& C = L->cls[c];
+    size_t lds = C.lds;
+    for (const BatchClass& D : L->cls)
+      if (D.maxlen == C.maxlen && D.waves == C.waves && D.pitch == C.pitch && D.lds > lds) lds = D.lds;
+    const hipError_t e = set_batched_lds(C.maxlen, C.waves, C.pitch, lds);
     if (e != hipSuccess) return hip_fail(e);
   }
   return batched_setup(inst, count, *L, *w, *geo, ws, st);
@@ -1064,10 +1062,9 @@ int jpet_mlem_batched_iterate(const jpet_instance* inst, int32_t count, int32_t 
   BatchLayout L;
   std::vector<Workspace> w;
   std::vector<Geo> geo;
-  int cus = 0;
-  int rc = batched_begin(inst, count, ws, ws_bytes, flags, st, &L, &w, &geo, &cus);
+  int rc = batched_begin(inst, count, ws, ws_bytes, flags, st, &L, &w, &geo);
   if (rc) return rc;
-  rc = batched_iterations(inst, count, n_iter, L, w, geo, ws, cus, true, st);
+  rc = batched_iterations(inst, count, n_iter, L, w, geo, ws, true, st);
   if (rc) return rc;
   if (stats) {
     for (int k = 0; k < count; ++k) {
@@ -1086,8 +1083,7 @@ int jpet_mlem_batched_graph_create(const jpet_instance* inst, int32_t count, int
   BatchLayout L;
   std::vector<Workspace> w;
   std::vector<Geo> geo;
-  int cus = 0;
-  int rc = batched_begin(inst, count, ws, ws_bytes, flags, st, &L, &w, &geo, &cus);
+  int rc = batched_begin(inst, count, ws, ws_bytes, flags, st, &L, &w, &geo);
   if (rc) return rc;
   // capture the iterations on a stream of the library's own, at the default priority
   hipStream_t cs = nullptr;
@@ -1096,7 +1092,7 @@ int jpet_mlem_batched_graph_create(const jpet_instance* inst, int32_t count, int
   hipGraph_t graph = nullptr;
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    rc = batched_iterations(inst, count, n_iter, L, w, geo, ws, cus, false, cs);
+    rc = batched_iterations(inst, count, n_iter, L, w, geo, ws, false, cs);
     e = hipStreamEndCapture(cs, &graph);
   }
   (void)hipStreamDestroy(cs);

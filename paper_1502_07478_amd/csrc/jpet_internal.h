@@ -203,7 +203,7 @@ struct BatchInst {
   Plan p;
   int32_t tiled;              // 1: binned pass inside the batched launch; 0: generic pass, launched apart
   int32_t index;              // position in the caller's instance array
-  int32_t cls;                // the persistent launch (class) serving it, -1: none
+  int32_t cls;                // the batched launch (class) serving it, -1: none
   int32_t pad;
   int64_t item_begin;         // its first work index within its class
   int64_t n;                  // events
@@ -215,11 +215,10 @@ struct BatchInst {
   unsigned long long* cnt;
 };
 
-// Work counter of a batched iteration's persistent pass.
+// Work list of one class of a batch: its workgroup items, counted on the device after preparation.
 struct BatchWork {
-  unsigned next;   // next work index, reset every iteration
-  unsigned total;  // workgroup items of all binned instances
-  unsigned pad[2];
+  unsigned total;  // workgroup items of the class's instances
+  unsigned pad[3];
 };
 
 constexpr int kInstPerWrite = 6;  // instances written per table-writing launch (by-value kernel argument)
@@ -265,15 +264,17 @@ hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_update(const Geo& g, const float* s, float* rho, const Workspace& ws, hipStream_t st);
 // batched: table of count instances in device memory; grid = total workgroups of the tiled ones
 hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t st);
-hipError_t launch_batched_reset(const BatchInst* table, int count, BatchWork* work, int nclasses, hipStream_t st);
+hipError_t launch_batched_reset(const BatchInst* table, int count, hipStream_t st);
 hipError_t launch_batched_work(BatchInst* table, int count, BatchWork* work, int nclasses, hipStream_t st);
-// the persistent pass over one class of a batch (table: the class's entries): 32-bit accumulators,
-// register cache maxlen (16 or 32), waves (8 or 16) wavefronts per workgroup, grid = resident
-// workgroups
-hipError_t launch_event_pass_persistent(const BatchInst* table, int count, BatchWork* work, int maxlen, int waves,
-                                        size_t lds_bytes, int grid, hipStream_t st);
-// raises a persistent pass's dynamic LDS limit (call before launching or capturing it)
-hipError_t set_persistent_lds(int maxlen, int waves, size_t lds_bytes);
+// the batched pass over one class of a batch (table: the class's entries): 32-bit accumulators,
+// register cache maxlen (16 or 32), waves (8 or 16) wavefronts per workgroup, region row pitch
+// (64, 128, 256, or 0 for any other), grid = an upper bound of the class's workgroup items
+hipError_t launch_event_pass_batched(const BatchInst* table, int count, const BatchWork* work, int maxlen, int waves,
+                                     int pitch, size_t lds_bytes, int64_t grid, hipStream_t st);
+// the pitch a batched class is compiled for: 64, 128 or 256, else 0 (a runtime value)
+inline int batched_pitch_class(int pitch) { return pitch == 64 || pitch == 128 || pitch == 256 ? pitch : 0; }
+// raises a batched pass's dynamic LDS limit (call before launching or capturing it)
+hipError_t set_batched_lds(int maxlen, int waves, int pitch, size_t lds_bytes);
 hipError_t launch_update_batched(const BatchInst* table, int count, int64_t max_npix, hipStream_t st);
 // value_only: l alone (out3[1], out3[2] are NaN, grad_rho must be null)
 hipError_t launch_loglik(const Geo& g, const Plan& p, int64_t n, const Workspace& ws, const float* rho,

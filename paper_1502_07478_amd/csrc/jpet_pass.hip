@@ -607,52 +607,29 @@ __global__ void __launch_bounds__(WAVES * 64, loglik_waves_per_simd<MAXLEN>())
                                                 red, evs);
 }
 
-// The same pass over many independent reconstructions, persistent: the grid is as many
-// workgroups as stay resident, and each workgroup pulls work indices from a counter until the
-// batch's items run out.  Work index w is item w - item_begin of the last instance (in table order,
-// heaviest items first) whose item_begin <= w.  The region's row pitch varies between instances;
-// each common pitch has its own compile-time copy of the pass (immediate LDS offsets).
-template <int MAXLEN, int WAVES>
+// The same pass over many independent reconstructions: one workgroup per workgroup item of a
+// class of instances.  Work index w = blockIdx.x is item w - item_begin of the last instance (in
+// table order, heaviest items first) whose item_begin <= w; the grid is an upper bound of the
+// class's items, and workgroups at or past its item count return at once.  Every instance of a
+// class has the same region row pitch, PITCH (0: a runtime value), so that the per-pixel LDS
+// addresses are immediates as in the single-image pass.
+template <int MAXLEN, int WAVES, int PITCH>
 __global__ void __launch_bounds__(WAVES * 64, pass_waves_per_simd<MAXLEN>())
-    k_event_pass_persistent(const BatchInst* __restrict__ inst, int count, BatchWork* __restrict__ work) {
+    k_event_pass_batched(const BatchInst* __restrict__ inst, int count, const BatchWork* __restrict__ work) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ PassShared ps;
-  __shared__ unsigned w_s;
-  const unsigned total = work->total;
-  for (;;) {
-    // w_s was last read before the previous item's barriers; every thread of the workgroup has
-    // left that item's LDS before the barrier below lets the next item start
-    if (threadIdx.x == 0) w_s = atomicAdd(&work->next, 1u);
-    __syncthreads();
-    const unsigned w = w_s;
-    if (w >= total) break;  // uniform over the workgroup
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (inst[mid].item_begin <= (int64_t)w) lo = mid;
-      else hi = mid - 1;
-    }
-    const BatchInst& I = inst[lo];
-    const BinItem it = I.items[(int64_t)w - I.item_begin];
-    switch (I.p.pitch) {
-      case 64:
-        event_pass_item<MAXLEN, WAVES, false, true, 64>(I.g, I.p, I.blocks, it, I.rho, I.acc, I.cnt, smem, ps,
-                                                        nullptr, nullptr, nullptr, nullptr);
-        break;
-      case 128:
-        event_pass_item<MAXLEN, WAVES, false, true, 128>(I.g, I.p, I.blocks, it, I.rho, I.acc, I.cnt, smem, ps,
-                                                         nullptr, nullptr, nullptr, nullptr);
-        break;
-      case 256:
-        event_pass_item<MAXLEN, WAVES, false, true, 256>(I.g, I.p, I.blocks, it, I.rho, I.acc, I.cnt, smem, ps,
-                                                         nullptr, nullptr, nullptr, nullptr);
-        break;
-      default:
-        event_pass_item<MAXLEN, WAVES, false, true, 0>(I.g, I.p, I.blocks, it, I.rho, I.acc, I.cnt, smem, ps,
-                                                       nullptr, nullptr, nullptr, nullptr);
-        break;
-    }
+  const unsigned w = blockIdx.x;
+  if (w >= work->total) return;  // uniform over the workgroup
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].item_begin <= (int64_t)w) lo = mid;
+    else hi = mid - 1;
   }
+  const BatchInst& I = inst[lo];
+  const BinItem it = I.items[(int64_t)w - I.item_begin];
+  event_pass_item<MAXLEN, WAVES, false, true, PITCH>(I.g, I.p, I.blocks, it, I.rho, I.acc, I.cnt, smem, ps, nullptr,
+                                                    nullptr, nullptr, nullptr);
 }
 
 // Work lists of a batch (one thread, after the preparation): each binned instance's first work
@@ -661,10 +638,7 @@ __global__ void __launch_bounds__(WAVES * 64, pass_waves_per_simd<MAXLEN>())
 __global__ void k_batched_work(BatchInst* __restrict__ table, int count, BatchWork* __restrict__ work,
                                int nclasses) {
   if (threadIdx.x != 0) return;
-  for (int c = 0; c < nclasses; ++c) {
-    work[c].total = 0u;
-    work[c].next = 0u;
-  }
+  for (int c = 0; c < nclasses; ++c) work[c].total = 0u;
   for (int k = 0; k < count; ++k) {
     const int c = table[k].cls;
     if (c < 0) continue;
@@ -803,15 +777,12 @@ __global__ void k_write_insts(InstWrite w, BatchInst* __restrict__ table) {
   if (t < w.count) table[w.first + t] = w.v[t];
 }
 
-// per-iteration counters of every instance (zero-denominator events, non-positive kappa pairs) and
-// the persistent pass's work counter
-__global__ void k_batched_reset(const BatchInst* __restrict__ table, int count, BatchWork* __restrict__ work,
-                                int nclasses) {
+// per-iteration counters of every instance: zero-denominator events, non-positive kappa pairs
+__global__ void k_batched_reset(const BatchInst* __restrict__ table, int count) {
   for (int k = threadIdx.x; k < count; k += blockDim.x) {
     table[k].cnt[C_ZERO_DEN] = 0ull;
     table[k].cnt[C_KAPPA_BAD] = 0ull;
   }
-  for (int c = threadIdx.x; c < nclasses; c += blockDim.x) work[c].next = 0u;
 }
 
 // rho = acc 2^-32 / s of every instance (blockIdx.y: table entry)
@@ -867,8 +838,8 @@ hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_batched_reset(const BatchInst* table, int count, BatchWork* work, int nclasses, hipStream_t st) {
-  hipLaunchKernelGGL(k_batched_reset, dim3(1), dim3(256), 0, st, table, count, work, nclasses);
+hipError_t launch_batched_reset(const BatchInst* table, int count, hipStream_t st) {
+  hipLaunchKernelGGL(k_batched_reset, dim3(1), dim3(256), 0, st, table, count);
   return hipGetLastError();
 }
 
@@ -878,40 +849,62 @@ hipError_t launch_batched_work(BatchInst* table, int count, BatchWork* work, int
 }
 
 namespace {
-template <int MAXLEN, int WAVES>
-hipError_t launch_persistent_t(const BatchInst* table, int count, BatchWork* work, size_t lds_bytes, int grid,
-                               hipStream_t st) {
-  // the dynamic LDS limit is raised beforehand (set_persistent_lds), outside any stream capture
-  auto kern = k_event_pass_persistent<MAXLEN, WAVES>;
+template <int MAXLEN, int WAVES, int PITCH>
+hipError_t launch_batched_t(const BatchInst* table, int count, const BatchWork* work, size_t lds_bytes, int64_t grid,
+                            hipStream_t st) {
+  // the dynamic LDS limit is raised beforehand (set_batched_lds), outside any stream capture
+  auto kern = k_event_pass_batched<MAXLEN, WAVES, PITCH>;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * WAVES), lds_bytes, st, table, count, work);
   return hipGetLastError();
 }
 
-const void* persistent_kernel(int maxlen, int waves) {
+template <int MAXLEN, int WAVES>
+const void* batched_kernel_p(int pitch) {
+  switch (pitch) {
+    case 64: return (const void*)k_event_pass_batched<MAXLEN, WAVES, 64>;
+    case 128: return (const void*)k_event_pass_batched<MAXLEN, WAVES, 128>;
+    case 256: return (const void*)k_event_pass_batched<MAXLEN, WAVES, 256>;
+    default: return (const void*)k_event_pass_batched<MAXLEN, WAVES, 0>;
+  }
+}
+
+const void* batched_kernel(int maxlen, int waves, int pitch) {
   switch (maxlen * 100 + waves) {
-    case 1608: return (const void*)k_event_pass_persistent<16, 8>;
-    case 3208: return (const void*)k_event_pass_persistent<32, 8>;
-    case 1616: return (const void*)k_event_pass_persistent<16, 16>;
-    case 3216: return (const void*)k_event_pass_persistent<32, 16>;
+    case 1608: return batched_kernel_p<16, 8>(pitch);
+    case 3208: return batched_kernel_p<32, 8>(pitch);
+    case 1616: return batched_kernel_p<16, 16>(pitch);
+    case 3216: return batched_kernel_p<32, 16>(pitch);
     default: return nullptr;
+  }
+}
+
+template <int MAXLEN, int WAVES>
+hipError_t launch_batched_p(const BatchInst* table, int count, const BatchWork* work, int pitch, size_t lds_bytes,
+                            int64_t grid, hipStream_t st) {
+  switch (pitch) {
+    case 64: return launch_batched_t<MAXLEN, WAVES, 64>(table, count, work, lds_bytes, grid, st);
+    case 128: return launch_batched_t<MAXLEN, WAVES, 128>(table, count, work, lds_bytes, grid, st);
+    case 256: return launch_batched_t<MAXLEN, WAVES, 256>(table, count, work, lds_bytes, grid, st);
+    default: return launch_batched_t<MAXLEN, WAVES, 0>(table, count, work, lds_bytes, grid, st);
   }
 }
 }  // namespace
 
-hipError_t launch_event_pass_persistent(const BatchInst* table, int count, BatchWork* work, int maxlen, int waves,
-                                        size_t lds_bytes, int grid, hipStream_t st) {
+hipError_t launch_event_pass_batched(const BatchInst* table, int count, const BatchWork* work, int maxlen, int waves,
+                                     int pitch, size_t lds_bytes, int64_t grid, hipStream_t st) {
   if (count <= 0 || grid <= 0) return hipSuccess;
+  if (grid > 0x7fffffffll) return hipErrorInvalidValue;
   switch (maxlen * 100 + waves) {
-    case 1608: return launch_persistent_t<16, 8>(table, count, work, lds_bytes, grid, st);
-    case 3208: return launch_persistent_t<32, 8>(table, count, work, lds_bytes, grid, st);
-    case 1616: return launch_persistent_t<16, 16>(table, count, work, lds_bytes, grid, st);
-    case 3216: return launch_persistent_t<32, 16>(table, count, work, lds_bytes, grid, st);
+    case 1608: return launch_batched_p<16, 8>(table, count, work, pitch, lds_bytes, grid, st);
+    case 3208: return launch_batched_p<32, 8>(table, count, work, pitch, lds_bytes, grid, st);
+    case 1616: return launch_batched_p<16, 16>(table, count, work, pitch, lds_bytes, grid, st);
+    case 3216: return launch_batched_p<32, 16>(table, count, work, pitch, lds_bytes, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t set_persistent_lds(int maxlen, int waves, size_t lds_bytes) {
-  const void* k = persistent_kernel(maxlen, waves);
+hipError_t set_batched_lds(int maxlen, int waves, int pitch, size_t lds_bytes) {
+  const void* k = batched_kernel(maxlen, waves, pitch);
   if (!k) return hipErrorInvalidValue;
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }

@@ -405,8 +405,8 @@ class ChunkedMLEM:
 
 
 class BatchedMLEM:
-    """Many independent reconstructions advanced together (jpet_mlem_batched_*): one persistent
-    event-pass launch per iteration for the whole batch.
+    """Many independent reconstructions advanced together (jpet_mlem_batched_*): per iteration one
+    event-pass launch per class of like instances, one workgroup per workgroup item.
 
     instances: list of (geometry, events float32 [n, 3], sensitivity or None, rho float32 [n_y, n_z]),
     all CUDA tensors on one device; each rho is updated in place by iterate() and run().  The events

@@ -60,7 +60,7 @@ def _store(path: str, key: str, entry: dict) -> None:
 
 
 def batchable(g: jpet.Geometry, code: int, n_events: int) -> bool:
-    """Plans a batched persistent pass can run: 32-bit accumulators, a register cache <= 32."""
+    """Plans the batched pass can run: 32-bit accumulators, a register cache <= 32."""
     if code == 3:
         return True
     info = jpet.launch_info(jpet.with_plan(g, code), n_events)
@@ -87,7 +87,7 @@ def time_plans(g: jpet.Geometry, events: torch.Tensor, codes, rho: torch.Tensor 
 
 def tune(g: jpet.Geometry, events: torch.Tensor, rho: torch.Tensor | None = None, candidates: int = 12,
          reps: int = 3, batched: bool = False) -> dict:
-    """Times the cost model's first `candidates` plans (for a batch: those a persistent batched
+    """Times the cost model's first `candidates` plans (for a batch: those the batched
     pass can run) and returns {"code", "ms", "model_code", "model_ms", "timed", "seconds"}."""
     t0 = time.perf_counter()
     n = events.shape[0]
