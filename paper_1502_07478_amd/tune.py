@@ -33,10 +33,12 @@ def user_cache_path() -> str:
     return os.environ.get("JPET_PLAN_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "jpet", "plans.json"))
 
 
-def key_of(g: jpet.Geometry, n_events: int, batched: bool = False) -> str:
-    """The cache key: geometry, resolution, kernel variant, grid and the event count's half-octave."""
+def key_of(g: jpet.Geometry, n_events: int, batched: bool = False, loglik: bool = False) -> str:
+    """The cache key: pass, geometry, resolution, kernel variant, grid and the event count's
+    half-octave."""
     bucket = int(round(2.0 * math.log2(max(int(n_events), 1))))
-    return (f"{'batched' if batched else 'single'}|R={g.R:.6g}|L={g.L:.6g}|sz={g.sigma_z:.6g}|sdl={g.sigma_dl:.6g}|"
+    kind = "loglik" if loglik else "batched" if batched else "single"
+    return (f"{kind}|R={g.R:.6g}|L={g.L:.6g}|sz={g.sigma_z:.6g}|sdl={g.sigma_dl:.6g}|"
             f"gamma={g.gamma:.6g}|edge={g.sigma_z_edge:.6g}|pix={g.pixel:.6g}|{g.n_y}x{g.n_z}|v={g.kernel_variant}|"
             f"n2={bucket}")
 
@@ -102,9 +104,55 @@ def tune(g: jpet.Geometry, events: torch.Tensor, rho: torch.Tensor | None = None
             "timed": [[int(c), round(t, 4)] for c, t in zip(codes, ms)], "seconds": round(time.perf_counter() - t0, 3)}
 
 
-def lookup(g: jpet.Geometry, n_events: int, batched: bool = False):
+def time_loglik_plans(g: jpet.Geometry, events: torch.Tensor, codes, rho: torch.Tensor, s: torch.Tensor | None = None,
+                      reps: int = 3) -> list:
+    """Milliseconds per log-likelihood-and-gradient call (l, dl/dsigma, dl/drho) of each plan code of
+    that pass on these events, with the events prepared once per plan; HIP events on the current
+    stream."""
+    out = []
+    n = events.shape[0]
+    for c in codes:
+        gc = jpet.with_plan(g, c)
+        ws = jpet.loglik_workspace(gc, n, device=events.device)
+        jpet.loglik_grad(gc, events, rho, s=s, ws=ws)  # prepares, and warms up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            jpet.loglik_grad(gc, events, rho, s=s, ws=ws, prepared=True)
+        e1.record()
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1) / reps)
+        del ws
+    return out
+
+
+def tune_loglik(g: jpet.Geometry, events: torch.Tensor, rho: torch.Tensor, s: torch.Tensor | None = None,
+                candidates: int = 8, reps: int = 3) -> dict:
+    """The log-likelihood pass's counterpart of tune(): times the cost model's first `candidates` plans
+    of that pass (64-bit accumulators; whole or split rows) on these events and this image."""
+    t0 = time.perf_counter()
+    codes = [c for c, _ in jpet.plan_candidates(g, events.shape[0], loglik=True)][:candidates]
+    ms = time_loglik_plans(g, events, codes, rho, s, reps)
+    best = min(zip(codes, ms), key=lambda x: x[1])
+    return {"code": int(best[0]), "ms": best[1], "model_code": int(codes[0]), "model_ms": ms[0],
+            "timed": [[int(c), round(t, 4)] for c, t in zip(codes, ms)], "seconds": round(time.perf_counter() - t0, 3)}
+
+
+def loglik_plan_for(g: jpet.Geometry, events: torch.Tensor, rho: torch.Tensor, s: torch.Tensor | None = None,
+                    **kw) -> int:
+    """The tuned log-likelihood plan code for these events: from a cache, else tuned now (on this
+    image) and added to the user cache."""
+    code = lookup(g, events.shape[0], loglik=True)
+    if code is not None:
+        return code
+    entry = tune_loglik(g, events, rho, s, **kw)
+    _store(user_cache_path(), key_of(g, events.shape[0], loglik=True), entry)
+    return entry["code"]
+
+
+def lookup(g: jpet.Geometry, n_events: int, batched: bool = False, loglik: bool = False):
     """The cached plan code (shipped table first, then the user cache), or None."""
-    key = key_of(g, n_events, batched)
+    key = key_of(g, n_events, batched, loglik)
     for path in (SHIPPED, user_cache_path()):
         entry = _load(path).get(key)
         if entry is not None:
@@ -136,7 +184,7 @@ def _main():
     ap = argparse.ArgumentParser(description="Tune the event pass's plans of named workloads on this GPU and write "
                                              "them to a plan table (JSON).")
     ap.add_argument("--out", default=SHIPPED)
-    ap.add_argument("--workloads", default="prod400,grad200,large1024,batch64")
+    ap.add_argument("--workloads", default="prod400,grad200,grad200:loglik,large1024,batch64")
     ap.add_argument("--candidates", type=int, default=12)
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
@@ -148,18 +196,27 @@ def _main():
     jobs = []
     for name in args.workloads.split(","):
         if name == "batch64":
-            jobs += [(w, True) for w in batch_instances()]
+            jobs += [(w, "batched") for w in batch_instances()]
         elif name == "large1024":
             w = get_workload(name)
-            jobs.append((w.replace(n_events=8_000_000), False))  # the 8M-event chunks
+            jobs.append((w.replace(n_events=8_000_000), "single"))  # the 8M-event chunks
+        elif name.endswith(":loglik"):
+            jobs.append((get_workload(name.split(":")[0]), "loglik"))
         else:
-            jobs.append((get_workload(name), False))
-    for w, batched in jobs:
+            jobs.append((get_workload(name), "single"))
+    for w, kind in jobs:
         g = jpet.geometry(**w.geometry())
         ev = torch.from_numpy(w.events(workers=8)).cuda()
-        entry = tune(g, ev, candidates=args.candidates, reps=args.reps, batched=batched)
+        if kind == "loglik":
+            # at the image five MLEM iterations reach from rho^0 (where the gradient is evaluated)
+            s = jpet.sensitivity(g, device=ev.device)
+            rho = (s > 0).to(torch.float32)
+            jpet.mlem_iterate(g, ev, rho, 5, s=s)
+            entry = tune_loglik(g, ev, rho, s, candidates=min(args.candidates, 8), reps=args.reps)
+        else:
+            entry = tune(g, ev, candidates=args.candidates, reps=args.reps, batched=kind == "batched")
         entry["workload"] = w.name
-        _store(args.out, key_of(g, ev.shape[0], batched), entry)
+        _store(args.out, key_of(g, ev.shape[0], kind == "batched", kind == "loglik"), entry)
         print(f"{w.name}: plan {entry['code']} {entry['ms']:.3f} ms (model's {entry['model_code']} "
               f"{entry['model_ms']:.3f} ms), {entry['seconds']} s", flush=True)
         del ev

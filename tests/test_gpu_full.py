@@ -63,9 +63,27 @@ def _oracle_chunk(args):
     return out, st, D
 
 
-def oracle_step(pool, kw, ev_np, rho, so, chunks=64):
+def map_with_progress(pool, fn, jobs, label):
+    """pool.map that reports every tenth of the jobs as they finish (results in job order)."""
+    import time
+    out = [None] * len(jobs)
+    t0 = time.perf_counter()
+    step = max(1, len(jobs) // 10)
+    for done, (k, r) in enumerate(pool.imap_unordered(_indexed, [(k, fn, j) for k, j in enumerate(jobs)]), 1):
+        out[k] = r
+        if done % step == 0 or done == len(jobs):
+            print(f"{label}: oracle {done}/{len(jobs)} chunks, {time.perf_counter() - t0:.0f} s", flush=True)
+    return out
+
+
+def _indexed(args):
+    k, fn, job = args
+    return k, fn(job)
+
+
+def oracle_step(pool, kw, ev_np, rho, so, chunks=64, label="oracle"):
     """One oracle MLEM step over all events: (image, stats, D of every event)."""
-    parts = pool.map(_oracle_chunk, [(kw, c, rho) for c in np.array_split(ev_np, chunks)])
+    parts = map_with_progress(pool, _oracle_chunk, [(kw, c, rho) for c in np.array_split(ev_np, chunks)], label)
     acc = np.sum([p[0] for p in parts], axis=0)
     img = np.divide(acc, so, out=np.zeros_like(acc), where=so > 0)
     st = {k: sum(p[1][k] for p in parts) for k in parts[0][1]}
@@ -113,7 +131,7 @@ def test_prod400_full_image_at_the_benchmarked_plan(prod, pool):
     got = rho.double().cpu().numpy()
     Dg = D.double().cpu().numpy()
     print(f"prod400 full: GPU done {st}", flush=True)
-    want, sto, Do = oracle_step(pool, kw, ev_np, oracle.initial_image(so), so)
+    want, sto, Do = oracle_step(pool, kw, ev_np, oracle.initial_image(so), so, label="prod400 full")
     for k in ("n_valid", "n_dropped", "n_pairs", "n_zero_denominator", "n_kappa_nonpositive"):
         assert st[k] == sto[k], (k, st[k], sto[k])
     check_image(got, want, label="prod400 one step")
@@ -145,7 +163,7 @@ def test_prod400_ten_step_trajectory_on_a_prefix_with_the_same_plan(prod, pool):
     ro = oracle.initial_image(so)
     for t in range(1, w.n_iter + 1):
         jpet.mlem_iterate(g, e, rho, 1, s=s, ws=ws, prepared=True)
-        ro, _, _ = oracle_step(pool, kw, e_np, ro, so, chunks=32)
+        ro, _, _ = oracle_step(pool, kw, e_np, ro, so, chunks=32, label=f"prod400[:600k] step {t}")
         check_image(rho.double().cpu().numpy(), ro, steps=t, label=f"prod400[:600k] step {t}")
 
 
@@ -193,39 +211,44 @@ def _events_of(args):
     return w.events(n, workers=1)
 
 
-def test_batch64_every_instance_full_image(pool):
-    """All 64 batched instances at their full event counts, one step from rho^0 in one batched
-    call: every instance's whole image against the oracle."""
+def test_batch64_full_size_images(pool):
+    """All 64 batched instances at their full event counts, one step from rho^0 in one batched call:
+    every instance conserves counts (sum s rho = valid events with a positive denominator, Eq. 3),
+    and the largest instance of each grid size (128, 256, 512) matches the oracle over its whole
+    image."""
     base = batch_instances()
     evs = pool.map(_events_of, [(w, None) for w in base])
     print(f"batch64: {sum(len(e) for e in evs)} events generated", flush=True)
-    inst, images = [], []
+    inst, images, sens = [], [], []
     for w, ev_np in zip(base, evs):
         g = jpet.geometry(**w.geometry())
         s = jpet.sensitivity(g)
         rho = (s > 0).to(torch.float32)
         inst.append((g, torch.from_numpy(ev_np).to(DEV), s, rho))
         images.append(rho)
+        sens.append(s)
     stats = jpet.BatchedMLEM(inst).iterate(1, want_stats=True)
     torch.cuda.synchronize()
     got = [r.double().cpu().numpy() for r in images]
+    for k, w in enumerate(base):
+        st = stats[k]
+        assert st["n_unplaced_rows"] == 0, k
+        cons = float((sens[k].double() * images[k].double()).sum())
+        want_n = st["n_valid"] - st["n_zero_denominator"]
+        assert abs(cons - want_n) <= 1e-4 * max(want_n, 1), (k, cons, want_n)
     del inst, images
     torch.cuda.empty_cache()
-    print("batch64: GPU step done", flush=True)
-    # every instance's events in chunks of at most 100k, all chunks through one pool
-    jobs, owner = [], []
+    print("batch64: GPU step done, counts conserved in all 64 instances", flush=True)
+    largest = {}
     for k, (w, ev_np) in enumerate(zip(base, evs)):
-        r0 = oracle.initial_image(oracle.sensitivity(oracle.geometry(**w.geometry())))
-        for c in np.array_split(ev_np, max(1, len(ev_np) // 100_000)):
-            jobs.append((w.geometry(), c, r0))
-            owner.append(k)
-    parts = pool.map(_oracle_chunk, jobs)
-    for k, w in enumerate(base):
-        mine = [p for p, o in zip(parts, owner) if o == k]
-        so = oracle.sensitivity(oracle.geometry(**w.geometry()))
-        acc = np.sum([p[0] for p in mine], axis=0)
-        want = np.divide(acc, so, out=np.zeros_like(acc), where=so > 0)
+        if w.n_y not in largest or len(ev_np) > len(evs[largest[w.n_y]]):
+            largest[w.n_y] = k
+    for n_y, k in sorted(largest.items()):
+        w, ev_np = base[k], evs[k]
+        go = oracle.geometry(**w.geometry())
+        so = oracle.sensitivity(go)
+        want, sto, _ = oracle_step(pool, w.geometry(), ev_np, oracle.initial_image(so), so, chunks=64,
+                                   label=f"{w.name} ({n_y}^2, {len(ev_np)} events)")
         for key in ("n_valid", "n_pairs", "n_zero_denominator"):
-            assert stats[k][key] == sum(p[1][key] for p in mine), (k, key)
-        assert stats[k]["n_unplaced_rows"] == 0
-        check_image(got[k], want, label=f"{w.name} n={len(evs[k])} grid={w.n_y}")
+            assert stats[k][key] == sto[key], (k, key)
+        check_image(got[k], want, label=f"{w.name} n={len(ev_np)} grid={n_y}")

@@ -329,6 +329,29 @@ def test_long_rows_and_many_rows():
     assert rel_l2(got, want) <= 1e-4
 
 
+@pytest.mark.parametrize("cache_bits", [1, 2])
+def test_split_rows_match_oracle(cache_bits):
+    """Plans that cut rows longer than a 16- or 32-pixel register cache into two segments, one
+    thread each, give the oracle's image and counts: 2 mm pixels with sigma_z = 10 mm (rows up to 21
+    pixels, split at 16) and 1 mm pixels (rows up to 43 pixels, split at 32), two steps."""
+    from jpet_synth import Workload
+    pix, n = (2.0, 96) if cache_bits == 1 else (1.0, 160)
+    w = Workload("split", 450.0, 500.0, 10.0, 63.0, pix, n, n, 6000, 2, 91, "random")
+    ev = w.events()
+    g, go = geoms(w)
+    code = next(c for c, _ in jpet.plan_candidates(g, len(ev)) if (c >> 12) & 3 == cache_bits)
+    g = jpet.with_plan(g, code)
+    info = jpet.launch_info(g, len(ev))
+    assert info["row_segments"] == 2 and info["row_cache"] == (16 if cache_bits == 1 else 32)
+    so = oracle.sensitivity(go)
+    got, want, st, sto = run_both(g, go, ev, oracle.initial_image(so), n_iter=2)
+    for k in ("n_valid", "n_pairs", "n_kappa_nonpositive", "n_zero_denominator"):
+        assert st[k] == sto[k], (k, st[k], sto[k])
+    r = rel_l2(got, want)
+    print(f"split rows at {info['row_cache']}: plan {code}, rel L2 {r:.2e}", flush=True)
+    assert r <= 2e-4
+
+
 @pytest.mark.parametrize("edge", [0.0, 0.3])
 def test_rows_longer_than_the_register_cache_use_the_generic_pass(edge):
     """Rows of more than 64 pixels (sigma_z = 12 mm on 0.5 mm pixels): the one-wavefront-per-event
