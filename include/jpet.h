@@ -285,6 +285,23 @@ int jpet_mlem_batched_graph_launch(jpet_batched_graph* graph, void* stream);
 /* Releases the graph (NULL is allowed); it must not be executing. */
 int jpet_mlem_batched_graph_destroy(jpet_batched_graph* graph);
 
+/* jpet_mlem_iterate without a caller workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid allocation).  The workspace
+ * is a device array of JPET_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held from the
+ * first call on that GPU until the process ends; the call allocates nothing.  Arguments and
+ * results are those of jpet_mlem_iterate, except:
+ *   - flags must be 0 (else JPET_EINVAL): every call prepares its events, and runs the planned
+ *     event pass;
+ *   - a geometry and event count whose workspace (jpet_mlem_workspace_size) exceeds
+ *     JPET_NOALLOC_SCRATCH_BYTES returns JPET_EWORKSPACE before anything is enqueued (about
+ *     300k events at 400 x 400 px of 2 mm, 500k at 64 x 64 px of 4 mm);
+ *   - all calls on one GPU share its array, which keeps the last call's contents: calls that
+ *     overlap on one GPU (different streams or threads without ordering between them) race and
+ *     give undefined results.  Order them on one stream or synchronise between them. */
+#define JPET_NOALLOC_SCRATCH_BYTES (256u * 1024u * 1024u)
+int jpet_mlem_iterate_noalloc(const jpet_geometry* g, const float* events, int64_t n, const float* s, float* rho,
+                              int32_t n_iter, uint32_t flags, jpet_stats* stats, void* stream);
+
 /* Launch shape the library picks for jpet_mlem_iterate on this geometry and event count
  * (diagnostics and tuning reports).  Host output. */
 typedef struct jpet_launch_info {

@@ -130,6 +130,8 @@ int do_prepare(const Geo& geo, const Plan& p, const float* events, int64_t n, co
 
 }  // namespace
 
+int record_hip_failure(hipError_t e) { return hip_fail(e); }
+
 // LDS row-pitch alignment of the binned pass's column-major region
 static const int kBankAlign = 64;
 

@@ -247,6 +247,9 @@ void plan_candidates(const jpet_geometry* g, double mask_sz, double mask_sdl, in
                      std::vector<PlanCand>* out);
 size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Workspace* out);
 
+// Records e as this thread's last HIP error (jpet_last_hip_error) and returns JPET_EHIP.
+int record_hip_failure(hipError_t e);
+
 // Kernel launchers (return the hipError_t of the launch).
 hipError_t launch_sensitivity(const Geo& g, float* s, hipStream_t st);
 hipError_t launch_direct_image(const Geo& g, double L, const float* events, int64_t n, float* img, hipStream_t st);

@@ -20,6 +20,8 @@ JPET_OK, JPET_EINVAL, JPET_EDOMAIN, JPET_EWORKSPACE, JPET_EHIP, JPET_ENOTSUP = 0
 JPET_WS_PREPARED = 1
 JPET_PASS_WAVE_PER_EVENT, JPET_PASS_THREAD_PER_EVENT = 2, 4
 JPET_LOGLIK_VALUE_ONLY = 8
+# bytes of the library's per-GPU scratch array behind jpet_mlem_iterate_noalloc (JPET_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 256 * 1024 * 1024
 
 
 class JpetError(RuntimeError):
@@ -93,6 +95,7 @@ def _lib():
         L.jpet_mlem_workspace_size.argtypes = [gp, i64, ctypes.POINTER(sz)]
         L.jpet_mlem_prepare.argtypes = [gp, vp, i64, vp, sz, vp]
         L.jpet_mlem_iterate.argtypes = [gp, vp, i64, vp, vp, i32, vp, sz, u32, sp, vp]
+        L.jpet_mlem_iterate_noalloc.argtypes = [gp, vp, i64, vp, vp, i32, u32, sp, vp]
         L.jpet_mlem_backproject.argtypes = [gp, vp, i64, vp, vp, vp, sz, u32, sp, vp]
         L.jpet_mlem_update.argtypes = [gp, vp, vp, vp, vp]
         L.jpet_loglik_workspace_size.argtypes = [gp, ctypes.POINTER(ctypes.c_double), i64, ctypes.POINTER(sz)]
@@ -250,6 +253,23 @@ def mlem_iterate(g: Geometry, events: torch.Tensor, rho: torch.Tensor, n_iter: i
                                   _ptr(ws), ws.numel(), (JPET_WS_PREPARED if prepared else 0) | _SPLIT[split],
                                   ctypes.byref(st) if st is not None else None, _stream(stream))
     _check(rc, "jpet_mlem_iterate")
+    return st.as_dict() if st is not None else None
+
+
+def mlem_iterate_noalloc(g: Geometry, events: torch.Tensor, rho: torch.Tensor, n_iter: int,
+                         s: torch.Tensor | None = None, want_stats: bool = False, stream=None):
+    """mlem_iterate with the library's own per-GPU scratch array as the workspace
+    (jpet_mlem_iterate_noalloc): no device allocation by the library or by this wrapper.  Calls on
+    one GPU share the array: order them on one stream."""
+    _events(events)
+    _need(rho, "rho", torch.float32, g.shape)
+    if s is not None:
+        _need(s, "s", torch.float32, g.shape)
+    st = Stats() if want_stats else None
+    rc = _lib().jpet_mlem_iterate_noalloc(ctypes.byref(g), _ptr(events), events.shape[0], _ptr(s), _ptr(rho),
+                                          int(n_iter), 0, ctypes.byref(st) if st is not None else None,
+                                          _stream(stream))
+    _check(rc, "jpet_mlem_iterate_noalloc")
     return st.as_dict() if st is not None else None
 
 
