@@ -237,12 +237,11 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
 /* Batched reconstruction: many independent list-mode MLEM problems (each with its own geometry,
  * resolution, event list, sensitivity and image) advanced together (one MLEM iteration of each is
  * the Sec. 4 listing with Eq. 3).  Instances that fit the binned pass are grouped into classes by
- * kernel configuration (wavefronts per workgroup, workgroups per CU, region row pitch); per
- * iteration each class is one launch with one workgroup per workgroup item of its instances, the
- * items in order of decreasing size.  Instances that fit only the generic pass get their own
+ * kernel configuration (register cache, wavefronts per workgroup, workgroups per CU, region row
+ * pitch); per iteration each class is one launch with one workgroup per workgroup item of its
+ * instances, the items in order of decreasing size.  Instances that fit only the generic pass get their own
  * launches.  A plan named in an instance's jpet_geometry.plan must be one the batched pass can run:
- * 32-bit accumulators and a register cache of at most 32 pixels (else JPET_EDOMAIN); plan 0 takes
- * the cost model's cheapest such plan.  Each instance's result is that of jpet_mlem_iterate on it
+ * 32-bit accumulators (else JPET_EDOMAIN); plan 0 takes the cost model's cheapest such plan.  Each instance's result is that of jpet_mlem_iterate on it
  * alone with the same plan, to FP32 rounding of the denominators.
  * Host struct; pointers as for jpet_mlem_iterate. */
 typedef struct jpet_instance {

@@ -381,13 +381,12 @@ size_t workspace_layout(const Plan& p, int64_t n, int64_t npix, void* base, Work
   return off;
 }
 
-// Layout of a batched workspace: the instance table, one work list per class, then one ordinary
-// workspace per instance.  Every instance that fits the binned pass takes the plan its geometry
-// names or the cost model's cheapest plan with 32-bit accumulators and a register cache of at most
-// 32 pixels (longer rows are split into two segments).  Instances whose plans share the wavefronts
-// per workgroup, the workgroups resident per CU and the region's row pitch (64, 128, 256 or any
-// other) form a class, served by one batched launch per iteration with the class's largest LDS
-// region and register cache; a batch of like instances is one class.  Within a class the table lists the instances heaviest workgroup
+// Layout of a batched workspace: the instance table, then one ordinary workspace per instance.
+// Every instance that fits the binned pass takes the plan its geometry names or the cost model's
+// cheapest plan with 32-bit accumulators.  Instances whose plans share the register cache, the
+// wavefronts per workgroup, the workgroups resident per CU and the region's row pitch (64, 128,
+// 256 or any other) form a class, served by one batched launch per iteration with the class's
+// largest LDS region; a batch of like instances is one class.  Within a class the table lists the instances heaviest workgroup
 // item first, so that the longest items are pulled earliest.  Instances that fit only the generic
 // pass follow the classes, with their own launches.
 struct BatchClass {
@@ -395,7 +394,7 @@ struct BatchClass {
   int maxlen = 0, waves = 0, wgs = 0;
   int pitch = 0;             // region row pitch the class is compiled for (0: a runtime value)
   size_t lds = 0;
-  int64_t grid = 0;          // upper bound of the class's workgroup items (sum of max_items)
+  int64_t items = 0;         // workgroup items of the class's instances (set once they are prepared)
 };
 
 struct BatchLayout {
@@ -404,12 +403,11 @@ struct BatchLayout {
   std::vector<int> order;       // table position -> instance
   std::vector<BatchClass> cls;  // the batched launches
   int64_t max_npix = 0;
-  size_t work_off = 0;          // BatchWork[cls.size()]
   size_t total = 0;
   bool invalid = false;         // a named plan does not fit its geometry or the batched pass
 };
 
-static bool batchable(const Plan& p) { return p.tiled && p.acc32 && p.maxlen <= 32 && !p.loglik; }
+static bool batchable(const Plan& p) { return p.tiled && p.acc32 && !p.loglik; }
 
 BatchLayout batch_layout(const jpet_instance* inst, int count) {
   BatchLayout L;
@@ -442,7 +440,7 @@ BatchLayout batch_layout(const jpet_instance* inst, int count) {
     }
     L.plan[k] = p;
     if (p.tiled) {
-      key[k] = (batched_pitch_class(p.pitch) * 32 + p.waves) * 8 + p.wgs;
+      key[k] = ((batched_pitch_class(p.pitch) * 128 + p.maxlen) * 32 + p.waves) * 8 + p.wgs;
       // pixels of a typical ellipse (App. B half sizes at theta = 0) times events per workgroup
       work[k] = (1.5 * g.sigma_dl / g.pixel) * (3.0 * g.sigma_z / sqrt(2.0) / g.pixel) * p.ev_per_wg;
     }
@@ -469,14 +467,10 @@ BatchLayout batch_layout(const jpet_instance* inst, int count) {
     }
     BatchClass& c = L.cls.back();
     ++c.count;
-    c.grid += p.max_items;
     c.maxlen = p.maxlen > c.maxlen ? p.maxlen : c.maxlen;
     if (p.lds_bytes > c.lds) c.lds = p.lds_bytes;
   }
-  for (BatchClass& c : L.cls) c.maxlen = c.maxlen <= 16 ? 16 : 32;
   size_t off = align_up(sizeof(BatchInst) * (size_t)count, 256);
-  L.work_off = off;
-  off = align_up(off + sizeof(BatchWork) * (L.cls.size() > 0 ? L.cls.size() : 1), 256);
   for (int k = 0; k < count; ++k) {
     L.off[k] = off;
     off = align_up(off + workspace_layout(L.plan[k], inst[k].n, npix_of(&inst[k].g), nullptr, nullptr), 256);
@@ -946,12 +940,39 @@ int jpet_mlem_batched_prepare(const jpet_instance* inst, int32_t count, void* ws
 
 }  // extern "C"
 
-// The setup of a batch's iterations, in stream order: the instance table, each binned instance's
-// first work index (from the items its preparation produced) and cleared accumulators.
+// Each class's workgroup items and each binned instance's first work index within its class, from
+// the items the instances' preparation produced (read back once; the stream is synchronised).
+static int batched_items(int32_t count, BatchLayout* L, const std::vector<Workspace>& w, hipStream_t st,
+                         std::vector<int64_t>* item_begin) {
+  std::vector<unsigned long long> items((size_t)count, 0ull);
+  hipError_t e;
+  for (int t = 0; t < count; ++t) {
+    const int k = L->order[t];
+    if (!L->plan[k].tiled) continue;
+    if ((e = hipMemcpyAsync(&items[k], w[k].cnt + C_ITEMS, sizeof(unsigned long long), hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+      return hip_fail(e);
+  }
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e);
+  item_begin->assign((size_t)count, 0);
+  for (BatchClass& C : L->cls) {
+    C.items = 0;
+    for (int t = C.first; t < C.first + C.count; ++t) {
+      const int k = L->order[t];
+      (*item_begin)[k] = C.items;
+      C.items += (int64_t)items[k];
+    }
+    if (C.items > 0x7fffffffll) return JPET_EINVAL;  // the launch grid is 32-bit
+  }
+  return JPET_OK;
+}
+
+// The setup of a batch's iterations, in stream order: the instance table (with each binned
+// instance's first work index) and cleared accumulators.
 static int batched_setup(const jpet_instance* inst, int32_t count, const BatchLayout& L,
-                         const std::vector<Workspace>& w, const std::vector<Geo>& geo, void* ws, hipStream_t st) {
+                         const std::vector<Workspace>& w, const std::vector<Geo>& geo,
+                         const std::vector<int64_t>& item_begin, void* ws, hipStream_t st) {
   BatchInst* table = reinterpret_cast<BatchInst*>(ws);
-  BatchWork* work = reinterpret_cast<BatchWork*>((char*)ws + L.work_off);
   hipError_t e;
   // written by small launches (by-value arguments) so that it stays stream-ordered
   for (int t0 = 0; t0 < count; t0 += kInstPerWrite) {
@@ -966,7 +987,7 @@ static int batched_setup(const jpet_instance* inst, int32_t count, const BatchLa
       b.p = L.plan[k];
       b.tiled = L.plan[k].tiled;
       b.index = k;
-      b.item_begin = 0;
+      b.item_begin = item_begin[k];
       b.cls = -1;
       for (int c = 0; c < (int)L.cls.size(); ++c)
         if (t0 + j >= L.cls[c].first && t0 + j < L.cls[c].first + L.cls[c].count) b.cls = c;
@@ -980,7 +1001,6 @@ static int batched_setup(const jpet_instance* inst, int32_t count, const BatchLa
     }
     if ((e = launch_write_insts(iw, table, st)) != hipSuccess) return hip_fail(e);
   }
-  if ((e = launch_batched_work(table, count, work, (int)L.cls.size(), st)) != hipSuccess) return hip_fail(e);
   for (int k = 0; k < count; ++k)
     if ((e = launch_fill_u64(w[k].acc, npix_of(&inst[k].g), st)) != hipSuccess) return hip_fail(e);
   return JPET_OK;
@@ -992,7 +1012,6 @@ static int batched_iterations(const jpet_instance* inst, int32_t count, int32_t 
                               const std::vector<Workspace>& w, const std::vector<Geo>& geo, void* ws, bool timing,
                               hipStream_t st) {
   BatchInst* table = reinterpret_cast<BatchInst*>(ws);
-  BatchWork* work = reinterpret_cast<BatchWork*>((char*)ws + L.work_off);
   hipError_t e;
   for (int it = 0; it < n_iter; ++it) {
     if ((e = launch_batched_reset(table, count, st)) != hipSuccess) return hip_fail(e);
@@ -1001,8 +1020,7 @@ static int batched_iterations(const jpet_instance* inst, int32_t count, int32_t 
         hipError_t r = hipSuccess;
         for (size_t c = 0; c < L.cls.size() && r == hipSuccess; ++c) {
           const BatchClass& C = L.cls[c];
-          r = launch_event_pass_batched(table + C.first, C.count, work + c, C.maxlen, C.waves, C.pitch, C.lds, C.grid,
-                                        st);
+          r = launch_event_pass_batched(table + C.first, C.count, C.maxlen, C.waves, C.pitch, C.lds, C.items, st);
         }
         return r;
       };
@@ -1046,7 +1064,9 @@ static int batched_begin(const jpet_instance* inst, int32_t count, void* ws, siz
     const hipError_t e = set_batched_lds(C.maxlen, C.waves, C.pitch, lds);
     if (e != hipSuccess) return hip_fail(e);
   }
-  return batched_setup(inst, count, *L, *w, *geo, ws, st);
+  std::vector<int64_t> item_begin;
+  if ((rc = batched_items(count, L, *w, st, &item_begin))) return rc;
+  return batched_setup(inst, count, *L, *w, *geo, item_begin, ws, st);
 }
 
 struct jpet_batched_graph {

@@ -205,7 +205,7 @@ struct BatchInst {
   int32_t index;              // position in the caller's instance array
   int32_t cls;                // the batched launch (class) serving it, -1: none
   int32_t pad;
-  int64_t item_begin;         // its first work index within its class
+  int64_t item_begin;         // its first work index within its class (item 0 of the instance)
   int64_t n;                  // events
   const unsigned char* blocks;
   const BinItem* items;
@@ -215,11 +215,6 @@ struct BatchInst {
   unsigned long long* cnt;
 };
 
-// Work list of one class of a batch: its workgroup items, counted on the device after preparation.
-struct BatchWork {
-  unsigned total;  // workgroup items of the class's instances
-  unsigned pad[3];
-};
 
 constexpr int kInstPerWrite = 6;  // instances written per table-writing launch (by-value kernel argument)
 struct InstWrite {
@@ -268,12 +263,11 @@ hipError_t launch_update(const Geo& g, const float* s, float* rho, const Workspa
 // batched: table of count instances in device memory; grid = total workgroups of the tiled ones
 hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t st);
 hipError_t launch_batched_reset(const BatchInst* table, int count, hipStream_t st);
-hipError_t launch_batched_work(BatchInst* table, int count, BatchWork* work, int nclasses, hipStream_t st);
 // the batched pass over one class of a batch (table: the class's entries): 32-bit accumulators,
-// register cache maxlen (16 or 32), waves (8 or 16) wavefronts per workgroup, region row pitch
-// (64, 128, 256, or 0 for any other), grid = an upper bound of the class's workgroup items
-hipError_t launch_event_pass_batched(const BatchInst* table, int count, const BatchWork* work, int maxlen, int waves,
-                                     int pitch, size_t lds_bytes, int64_t grid, hipStream_t st);
+// register cache maxlen (16, 32, 48 or 64), waves (8 or 16) wavefronts per workgroup, region row pitch
+// (64, 128, 256, or 0 for any other), one workgroup per item of the class (items in total)
+hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxlen, int waves, int pitch,
+                                     size_t lds_bytes, int64_t items, hipStream_t st);
 // the pitch a batched class is compiled for: 64, 128 or 256, else 0 (a runtime value)
 inline int batched_pitch_class(int pitch) { return pitch == 64 || pitch == 128 || pitch == 256 ? pitch : 0; }
 // raises a batched pass's dynamic LDS limit (call before launching or capturing it)

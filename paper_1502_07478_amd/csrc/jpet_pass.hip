@@ -481,30 +481,29 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       }
       if (nbad) atomicAdd(&ps.bad, (unsigned)nbad);
 
-      // per-event denominators
+      // per-event denominators: a segmented reduction over the wavefront's rows, one event at a
+      // time (a wavefront holds rows of a few events), then one double-precision LDS add per event
+      // and wavefront.  (Adding every row's partial sum with its own LDS atomic instead puts all
+      // lanes of a wavefront on two or three addresses; measured 5% slower at 400x400.)
       double* Dc = ps.D[bi % 3];
-      if constexpr (GRAD && !VALUE) {
-        // segmented reduction over the wavefront's rows, one event at a time
+      {
         unsigned long long act = __ballot(len > 0);
         while (act) {
           const int leader = __ffsll((long long)act) - 1;
           const int el = __builtin_amdgcn_readlane(e, leader);
           const bool mine = len > 0 && e == el;
           const float v = wave_sum_dpp(mine ? D : 0.0f);
-          if (lane == 0) atomicAdd(&Dc[el], (double)v);
-          const float vu = wave_sum_dpp(mine ? Du : 0.0f);
-          const float vw = wave_sum_dpp(mine ? Dw : 0.0f);
-          if (lane == 0) {
-            atomicAdd(&gsh->Du[bi % 3][el], vu);
-            atomicAdd(&gsh->Dw[bi % 3][el], vw);
+          if (lane == 0) unsafeAtomicAdd(&Dc[el], (double)v);
+          if constexpr (GRAD && !VALUE) {
+            const float vu = wave_sum_dpp(mine ? Du : 0.0f);
+            const float vw = wave_sum_dpp(mine ? Dw : 0.0f);
+            if (lane == 0) {
+              atomicAdd(&gsh->Du[bi % 3][el], vu);
+              atomicAdd(&gsh->Dw[bi % 3][el], vw);
+            }
           }
           act &= ~__ballot(mine);
         }
-      } else {
-        // every row adds its partial sum in double precision: the LDS atomic unit does the
-        // reduction (no VALU work beyond the conversion), and FP64 sums of FP32 partials do not
-        // depend on the order of the additions to FP32 precision
-        if (len > 0) unsafeAtomicAdd(&Dc[e], (double)D);
       }
       // batch bi + 1 accumulates into D[(bi + 1) % 3], last read (as batch bi - 2's) before the
       // previous barrier
@@ -608,18 +607,17 @@ __global__ void __launch_bounds__(WAVES * 64, loglik_waves_per_simd<MAXLEN>())
 }
 
 // The same pass over many independent reconstructions: one workgroup per workgroup item of a
-// class of instances.  Work index w = blockIdx.x is item w - item_begin of the last instance (in
-// table order, heaviest items first) whose item_begin <= w; the grid is an upper bound of the
-// class's items, and workgroups at or past its item count return at once.  Every instance of a
-// class has the same region row pitch, PITCH (0: a runtime value), so that the per-pixel LDS
-// addresses are immediates as in the single-image pass.
+// class of instances (the grid is the class's item count, total).  Work index w = blockIdx.x is
+// item w - item_begin of the last instance (in table order, heaviest items first) whose
+// item_begin <= w.  Every instance of a class has the same region row pitch, PITCH (0: a runtime
+// value), so that the per-pixel LDS addresses are immediates as in the single-image pass.
 template <int MAXLEN, int WAVES, int PITCH>
 __global__ void __launch_bounds__(WAVES * 64, pass_waves_per_simd<MAXLEN>())
-    k_event_pass_batched(const BatchInst* __restrict__ inst, int count, const BatchWork* __restrict__ work) {
+    k_event_pass_batched(const BatchInst* __restrict__ inst, int count, unsigned total) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ PassShared ps;
   const unsigned w = blockIdx.x;
-  if (w >= work->total) return;  // uniform over the workgroup
+  if (w >= total) return;  // uniform over the workgroup
   int lo = 0, hi = count - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -630,21 +628,6 @@ __global__ void __launch_bounds__(WAVES * 64, pass_waves_per_simd<MAXLEN>())
   const BinItem it = I.items[(int64_t)w - I.item_begin];
   event_pass_item<MAXLEN, WAVES, false, true, PITCH>(I.g, I.p, I.blocks, it, I.rho, I.acc, I.cnt, smem, ps, nullptr,
                                                     nullptr, nullptr, nullptr);
-}
-
-// Work lists of a batch (one thread, after the preparation): each binned instance's first work
-// index within its class, in table order, from the items its preparation produced, and each
-// class's total.
-__global__ void k_batched_work(BatchInst* __restrict__ table, int count, BatchWork* __restrict__ work,
-                               int nclasses) {
-  if (threadIdx.x != 0) return;
-  for (int c = 0; c < nclasses; ++c) work[c].total = 0u;
-  for (int k = 0; k < count; ++k) {
-    const int c = table[k].cls;
-    if (c < 0) continue;
-    table[k].item_begin = (int64_t)work[c].total;
-    work[c].total += (unsigned)table[k].cnt[C_ITEMS];
-  }
 }
 
 // Generic pass for geometries whose rows or regions do not fit the tiled pass: one wavefront per
@@ -843,18 +826,12 @@ hipError_t launch_batched_reset(const BatchInst* table, int count, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_batched_work(BatchInst* table, int count, BatchWork* work, int nclasses, hipStream_t st) {
-  hipLaunchKernelGGL(k_batched_work, dim3(1), dim3(64), 0, st, table, count, work, nclasses);
-  return hipGetLastError();
-}
-
 namespace {
 template <int MAXLEN, int WAVES, int PITCH>
-hipError_t launch_batched_t(const BatchInst* table, int count, const BatchWork* work, size_t lds_bytes, int64_t grid,
-                            hipStream_t st) {
+hipError_t launch_batched_t(const BatchInst* table, int count, unsigned items, size_t lds_bytes, hipStream_t st) {
   // the dynamic LDS limit is raised beforehand (set_batched_lds), outside any stream capture
   auto kern = k_event_pass_batched<MAXLEN, WAVES, PITCH>;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * WAVES), lds_bytes, st, table, count, work);
+  hipLaunchKernelGGL(kern, dim3(items), dim3(64 * WAVES), lds_bytes, st, table, count, items);
   return hipGetLastError();
 }
 
@@ -872,33 +849,42 @@ const void* batched_kernel(int maxlen, int waves, int pitch) {
   switch (maxlen * 100 + waves) {
     case 1608: return batched_kernel_p<16, 8>(pitch);
     case 3208: return batched_kernel_p<32, 8>(pitch);
+    case 4808: return batched_kernel_p<48, 8>(pitch);
+    case 6408: return batched_kernel_p<64, 8>(pitch);
     case 1616: return batched_kernel_p<16, 16>(pitch);
     case 3216: return batched_kernel_p<32, 16>(pitch);
+    case 4816: return batched_kernel_p<48, 16>(pitch);
+    case 6416: return batched_kernel_p<64, 16>(pitch);
     default: return nullptr;
   }
 }
 
 template <int MAXLEN, int WAVES>
-hipError_t launch_batched_p(const BatchInst* table, int count, const BatchWork* work, int pitch, size_t lds_bytes,
-                            int64_t grid, hipStream_t st) {
+hipError_t launch_batched_p(const BatchInst* table, int count, int pitch, unsigned items, size_t lds_bytes,
+                            hipStream_t st) {
   switch (pitch) {
-    case 64: return launch_batched_t<MAXLEN, WAVES, 64>(table, count, work, lds_bytes, grid, st);
-    case 128: return launch_batched_t<MAXLEN, WAVES, 128>(table, count, work, lds_bytes, grid, st);
-    case 256: return launch_batched_t<MAXLEN, WAVES, 256>(table, count, work, lds_bytes, grid, st);
-    default: return launch_batched_t<MAXLEN, WAVES, 0>(table, count, work, lds_bytes, grid, st);
+    case 64: return launch_batched_t<MAXLEN, WAVES, 64>(table, count, items, lds_bytes, st);
+    case 128: return launch_batched_t<MAXLEN, WAVES, 128>(table, count, items, lds_bytes, st);
+    case 256: return launch_batched_t<MAXLEN, WAVES, 256>(table, count, items, lds_bytes, st);
+    default: return launch_batched_t<MAXLEN, WAVES, 0>(table, count, items, lds_bytes, st);
   }
 }
 }  // namespace
 
-hipError_t launch_event_pass_batched(const BatchInst* table, int count, const BatchWork* work, int maxlen, int waves,
-                                     int pitch, size_t lds_bytes, int64_t grid, hipStream_t st) {
-  if (count <= 0 || grid <= 0) return hipSuccess;
-  if (grid > 0x7fffffffll) return hipErrorInvalidValue;
+hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxlen, int waves, int pitch,
+                                     size_t lds_bytes, int64_t items, hipStream_t st) {
+  if (count <= 0 || items <= 0) return hipSuccess;
+  if (items > 0x7fffffffll) return hipErrorInvalidValue;
+  const unsigned n = (unsigned)items;
   switch (maxlen * 100 + waves) {
-    case 1608: return launch_batched_p<16, 8>(table, count, work, pitch, lds_bytes, grid, st);
-    case 3208: return launch_batched_p<32, 8>(table, count, work, pitch, lds_bytes, grid, st);
-    case 1616: return launch_batched_p<16, 16>(table, count, work, pitch, lds_bytes, grid, st);
-    case 3216: return launch_batched_p<32, 16>(table, count, work, pitch, lds_bytes, grid, st);
+    case 1608: return launch_batched_p<16, 8>(table, count, pitch, n, lds_bytes, st);
+    case 3208: return launch_batched_p<32, 8>(table, count, pitch, n, lds_bytes, st);
+    case 4808: return launch_batched_p<48, 8>(table, count, pitch, n, lds_bytes, st);
+    case 6408: return launch_batched_p<64, 8>(table, count, pitch, n, lds_bytes, st);
+    case 1616: return launch_batched_p<16, 16>(table, count, pitch, n, lds_bytes, st);
+    case 3216: return launch_batched_p<32, 16>(table, count, pitch, n, lds_bytes, st);
+    case 4816: return launch_batched_p<48, 16>(table, count, pitch, n, lds_bytes, st);
+    case 6416: return launch_batched_p<64, 16>(table, count, pitch, n, lds_bytes, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -21,9 +21,7 @@ hipError_t launch_update(const Geo&, const float*, float*, const Workspace&, hip
 }
 hipError_t launch_write_insts(const InstWrite&, BatchInst*, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_batched_reset(const BatchInst*, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_batched_work(BatchInst*, int, BatchWork*, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_event_pass_batched(const BatchInst*, int, const BatchWork*, int, int, int, size_t, int64_t,
-                                     hipStream_t) {
+hipError_t launch_event_pass_batched(const BatchInst*, int, int, int, int, size_t, int64_t, hipStream_t) {
   return hipErrorNotSupported;
 }
 hipError_t set_batched_lds(int, int, int, size_t) { return hipErrorNotSupported; }
