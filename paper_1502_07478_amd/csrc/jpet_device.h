@@ -53,6 +53,23 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Lane k's value of v, as a wavefront-uniform value.
+__device__ __forceinline__ float lane_value(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+// Sums over each half of a wavefront (all lanes active): the row sums as above, then one row
+// broadcast adds row 0 into row 1 and row 2 into row 3, so that lane 31 holds the sum of lanes
+// 0-31 and lane 63 the sum of lanes 32-63.
+__device__ __forceinline__ float half_sums_dpp(float v) {
+  v += dpp_f<0xB1>(v);
+  v += dpp_f<0x4E>(v);
+  v += dpp_f<0x141>(v);
+  v += dpp_f<0x140>(v);
+  v += dpp_f<0x142, 0xa>(v);
+  return v;
+}
+
 __device__ inline int wave_max_i(int v) {
 #pragma unroll
   for (int off = WAVE / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, WAVE));

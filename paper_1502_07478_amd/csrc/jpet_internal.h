@@ -88,11 +88,16 @@ static_assert(sizeof(EvRow) == 80, "EvRow is copied to LDS in 16-byte units");
 constexpr uint32_t kWordCol = 0, kWordRow = 8, kWordLen = 17, kWordEv = 24;
 
 // A batch block: ev_per_batch per-event constants (EvRow for the MLEM pass, EvConst for the
-// log-likelihood pass), then one thread word per thread of the workgroup, then for each wavefront
-// its longest row (pixels; bit kGuardBit set when a row of the wavefront may reach kappa <= 0 and
-// needs the per-pixel test) and its shortest non-empty row.
+// log-likelihood pass), then one thread word per thread of the workgroup, then two words per
+// wavefront:
+//   its longest row (pixels; bit kGuardBit set when a row of the wavefront may reach kappa <= 0 and
+//   needs the per-pixel test);
+//   its shortest non-empty row (bits 0-7) and, with bit kHalfBit set, the one event of each
+//   half-wavefront's rows: lanes 0-31 in bits 8-12, lanes 32-63 in bits 16-20 (event 0 for a half
+//   with no rows).
 constexpr int kBlockTailWords = 2;
 constexpr uint32_t kGuardBit = 31;
+constexpr uint32_t kHalfBit = 31, kHalfLo = 8, kHalfHi = 16;
 
 // Spatial binning of events and launch shape of the tiled event pass.
 //

@@ -42,8 +42,13 @@ struct RowF {
   float kap0, dkap, gs0, dgs, qa, qb, qc;
 };
 
+// A register-cache entry that pass 2 does not read: any value, set by no instruction (keeping the
+// previous batch's value would keep the whole cache live through pass 1).
+__device__ __forceinline__ float unread() { return __builtin_nondeterministic_value(0.0f); }
+
 // Pass 1 along one row.  Chunks below the wavefront's shortest row (wmin, uniform) need no row-end
-// mask; idle lanes carry row constants that make every kernel value 0.
+// mask; idle lanes carry row constants that make every kernel value 0.  Chunks from the
+// wavefront's longest row (wl) on are skipped, and their register-cache entries left unset.
 template <int MAXLEN, bool GUARD>
 __device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __restrict__ rho_s, int base, int pitch,
                                        int len, int wmin, int wl, float (&m)[MAXLEN], int* nbad) {
@@ -94,7 +99,7 @@ __device__ __forceinline__ float pass1(const RowF& rk, float qa, const float* __
       }
     } else {
 #pragma unroll
-      for (int jj = 0; jj < kChunk; ++jj) m[j0 + jj] = 0.0f;
+      for (int jj = 0; jj < kChunk; ++jj) m[j0 + jj] = unread();
     }
   }
   return D;
@@ -195,7 +200,7 @@ __device__ __forceinline__ void pass1g(const RowF& rk, const RowD& rd, float qa,
       }
     } else {
 #pragma unroll
-      for (int jj = 0; jj < kChunk; ++jj) m[j0 + jj] = 0.0f;
+      for (int jj = 0; jj < kChunk; ++jj) m[j0 + jj] = unread();
     }
   }
 }
@@ -298,7 +303,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
   copy_consts(blk0, ev_lds, cbytes, tid);
   uint32_t word = reinterpret_cast<const uint32_t*>(blk0 + cbytes)[tid];
   uint32_t wlw = *reinterpret_cast<const uint32_t*>(blk0 + wl_off);
-  int wn = *reinterpret_cast<const int*>(blk0 + wn_off);
+  uint32_t wnw = *reinterpret_cast<const uint32_t*>(blk0 + wn_off);
   if (tid < kMaxBatch) {
     ps.D[0][tid] = 0.0;
     ps.D[1][tid] = 0.0;
@@ -360,7 +365,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
           pass2g<MAXLEN>(m, invD, pbase, pitch, n2, pwn, pwl, reinterpret_cast<double*>(acc_s));
         }
         const int nbp = min(p.ev_per_batch, it.count - (bi - 1) * p.ev_per_batch);
-        if (tid < nbp) {  // the batch slot's own sums (one thread each, in LDS, not registers)
+        if (wave == 0 && tid < nbp) {  // the batch slot's own sums (one thread each, in LDS, not registers)
           const double De = Dp[tid];
           if (De > 0.0) {
             gsh->sum[0][tid] += log(De);
@@ -385,9 +390,9 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
           pass2<MAXLEN, false>(m, sc, pbase, pitch, n2, pwn, pwl, acc_s);
         }
         const int nbp = min(p.ev_per_batch, it.count - (bi - 1) * p.ev_per_batch);
-        if (tid < nbp && !(Dp[tid] > 0.0)) atomicAdd(&ps.zero, 1u);
+        if (wave == 0 && tid < nbp && !(Dp[tid] > 0.0)) atomicAdd(&ps.zero, 1u);
         // the denominators themselves (with P's constant factor), by input position
-        if (D_out && tid < nbp)
+        if (D_out && wave == 0 && tid < nbp)
           D_out[evs[it.start + (bi - 1) * p.ev_per_batch + tid].index] = (float)(Dp[tid] * g.cnorm);
       }
     }
@@ -396,15 +401,15 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       const unsigned char* evb = ev_lds + buf * cbytes;  // this batch's constants
       const int wl = (int)(wlw & 0x7fffffffu);
       const bool guard = (wlw >> kGuardBit) != 0u;  // wavefront-uniform
+      const int wn = (int)(wnw & 0xffu);
       // prefetch the next batch: constants into the other LDS buffer, this thread's next word
-      uint32_t next = 0u, wlw_next = 0u;
-      int wn_next = 0;
+      uint32_t next = 0u, wlw_next = 0u, wnw_next = 0u;
       if (bi + 1 < nbatch) {
         const unsigned char* blk = blk0 + (size_t)(bi + 1) * (size_t)p.batch_bytes;
         copy_consts(blk, ev_lds + (buf ^ 1) * cbytes, cbytes, tid);
         next = reinterpret_cast<const uint32_t*>(blk + cbytes)[tid];
         wlw_next = *reinterpret_cast<const uint32_t*>(blk + wl_off);
-        wn_next = *reinterpret_cast<const int*>(blk + wn_off);
+        wnw_next = *reinterpret_cast<const uint32_t*>(blk + wn_off);
       }
 
       // this thread's row
@@ -413,11 +418,11 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       int base = 0;
       RowF rk = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 1e30f};  // idle lane: every kernel value is 0
       RowD rd = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-      if (len > 0) {
-        const int kl = (int)((word >> kWordCol) & 255u);
-        const int rl = (int)((word >> kWordRow) & 511u);
-        const float rlf = (float)rl;
-        if constexpr (GRAD) {
+      if constexpr (GRAD) {
+        if (len > 0) {
+          const int kl = (int)((word >> kWordCol) & 255u);
+          const int rl = (int)((word >> kWordRow) & 511u);
+          const float rlf = (float)rl;
           const EvConst& c = reinterpret_cast<const EvConst*>(evb)[e];
           // region-relative coordinates: the row's y, y - y~, and z of its first pixel - z~ - t (y - y~)
           const float Y = fmaf(rlf, pixf, Yb);
@@ -445,20 +450,27 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
             rd.Klh = 0.5f * iw * Y * fmaf(c.A2, Y, c.A3 * dy);
             rd.cw = cwf - 0.5f * iS * iw * c.Q3s * dy * dy;
           }
-        } else {
-          // the row constants from the event's polynomials in the region row (see EvRow)
-          const EvRow& c = reinterpret_cast<const EvRow*>(evb)[e];
-          const float b10 = fmaf(pixf, (float)(kl + off_s[rl]), fmaf(c.BT, rlf, c.B0));
-          const float kb = fmaf(c.KB1, rlf, c.KB0);
-          const float gb = fmaf(c.GB1, rlf, c.GB0);
-          rk.kap0 = fmaf(kb, b10, fmaf(fmaf(c.K2, rlf, c.K1), rlf, c.K0));
-          rk.dkap = kb * pixf;
-          rk.gs0 = fmaf(gb, b10, fmaf(fmaf(c.S2, rlf, c.S1), rlf, c.S0));
-          rk.dgs = gb * pixf;
-          rk.qa = c.qa;
-          rk.qb = c.QB * b10;
-          rk.qc = fmaf(c.s2u * b10, b10, fmaf(fmaf(c.Q2, rlf, c.Q1), rlf, c.Q0));
+          base = kl * pitch + rl;
         }
+      } else {
+        // the row constants from the event's polynomials in the region row (see EvRow), in every
+        // lane (an idle lane's word is 0: event 0, the region's first row and column, finite
+        // values); idle lanes then take kappa = 1 and S q = 1e30, so that every kernel value is 0
+        const int kl = (int)((word >> kWordCol) & 255u);
+        const int rl = (int)((word >> kWordRow) & 511u);
+        const float rlf = (float)rl;
+        const EvRow& c = reinterpret_cast<const EvRow*>(evb)[e];
+        const float b10 = fmaf(pixf, (float)(kl + off_s[rl]), fmaf(c.BT, rlf, c.B0));
+        const float kb = fmaf(c.KB1, rlf, c.KB0);
+        const float gb = fmaf(c.GB1, rlf, c.GB0);
+        const bool act = len > 0;
+        rk.kap0 = act ? fmaf(kb, b10, fmaf(fmaf(c.K2, rlf, c.K1), rlf, c.K0)) : 1.0f;
+        rk.dkap = act ? kb * pixf : 0.0f;
+        rk.gs0 = fmaf(gb, b10, fmaf(fmaf(c.S2, rlf, c.S1), rlf, c.S0));
+        rk.dgs = gb * pixf;
+        rk.qa = c.qa;
+        rk.qb = c.QB * b10;
+        rk.qc = act ? fmaf(c.s2u * b10, b10, fmaf(fmaf(c.Q2, rlf, c.Q1), rlf, c.Q0)) : 1e30f;
         base = kl * pitch + rl;
       }
 
@@ -481,12 +493,37 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       }
       if (nbad) atomicAdd(&ps.bad, (unsigned)nbad);
 
-      // per-event denominators: a segmented reduction over the wavefront's rows, one event at a
-      // time (a wavefront holds rows of a few events), then one double-precision LDS add per event
-      // and wavefront.  (Adding every row's partial sum with its own LDS atomic instead puts all
-      // lanes of a wavefront on two or three addresses; measured 5% slower at 400x400.)
+      // per-event denominators: a reduction over the wavefront's rows, then one double-precision
+      // LDS add per event and wavefront.  In most wavefronts (the rings) each half holds rows of
+      // one event (decided at prepare time): one reduction gives both halves' sums, which lanes
+      // 31 and 63 hold.  Otherwise a segmented reduction takes one event at a time.  (Adding
+      // every row's partial sum with its own LDS atomic instead puts all lanes of a wavefront on
+      // two or three addresses; measured 5% slower at 400x400.)
       double* Dc = ps.D[bi % 3];
-      {
+      if (wnw >> kHalfBit) {
+        const int elo = (int)((wnw >> kHalfLo) & 31u), ehi = (int)((wnw >> kHalfHi) & 31u);
+        const float h = half_sums_dpp(len > 0 ? D : 0.0f);
+        const float lo = lane_value(h, 31), hi = lane_value(h, 63);
+        if (lane == 0) {
+          if (elo == ehi) {
+            unsafeAtomicAdd(&Dc[elo], (double)lo + (double)hi);
+          } else {
+            unsafeAtomicAdd(&Dc[elo], (double)lo);
+            unsafeAtomicAdd(&Dc[ehi], (double)hi);
+          }
+        }
+        if constexpr (GRAD && !VALUE) {
+          const float hu = half_sums_dpp(len > 0 ? Du : 0.0f), hw = half_sums_dpp(len > 0 ? Dw : 0.0f);
+          const float ulo = lane_value(hu, 31), uhi = lane_value(hu, 63);
+          const float vlo = lane_value(hw, 31), vhi = lane_value(hw, 63);
+          if (lane == 0) {
+            atomicAdd(&gsh->Du[bi % 3][elo], ulo);
+            atomicAdd(&gsh->Du[bi % 3][ehi], uhi);
+            atomicAdd(&gsh->Dw[bi % 3][elo], vlo);
+            atomicAdd(&gsh->Dw[bi % 3][ehi], vhi);
+          }
+        }
+      } else {
         unsigned long long act = __ballot(len > 0);
         while (act) {
           const int leader = __ffsll((long long)act) - 1;
@@ -507,7 +544,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       }
       // batch bi + 1 accumulates into D[(bi + 1) % 3], last read (as batch bi - 2's) before the
       // previous barrier
-      if (tid < kMaxBatch) {
+      if (wave == 0 && tid < kMaxBatch) {
         ps.D[(bi + 1) % 3][tid] = 0.0;
         if constexpr (GRAD) {
           gsh->Du[(bi + 1) % 3][tid] = 0.0f;
@@ -521,7 +558,7 @@ __device__ __forceinline__ void event_pass_item(const Geo& g, const Plan& p, con
       pwn = wn;
       word = next;
       wlw = wlw_next;
-      wn = wn_next;
+      wnw = wnw_next;
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();

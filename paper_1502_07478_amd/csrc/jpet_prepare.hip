@@ -424,9 +424,24 @@ __global__ void __launch_bounds__(1024) k_build_batches(Geo g, Plan p, const Eve
       const int wl = wave_max_i(len);
       const int wmin = -wave_max_i(len > 0 ? -len : -wl);  // shortest non-empty row (0: none)
       const bool wguard = __any(guard);
+      // does each half-wavefront hold rows of one event only (the pass then reduces the
+      // denominators per half, without the per-event loop)?
+      const int ev = (int)((word >> kWordEv) & 31u);
+      const unsigned long long act = __ballot(len > 0);
+      const unsigned long long half = lane < 32 ? 0xffffffffull : 0xffffffff00000000ull;
+      const unsigned long long mine = act & half;
+      const int lead = mine ? __ffsll((long long)mine) - 1 : (lane & 32);
+      const int ev_lead = __shfl(ev, lead, WAVE);
+      const bool split = __any(len > 0 && ev != ev_lead);
+      // (a half with no rows takes the other half's event)
+      int ev_lo = __shfl(ev_lead, 0, WAVE), ev_hi = __shfl(ev_lead, 32, WAVE);
+      if (!(act & 0xffffffffull)) ev_lo = ev_hi;
+      if (!(act >> 32)) ev_hi = ev_lo;
       if (lane == 0) {
         words[64 * p.waves + (tid >> 6)] = (uint32_t)wl | (wguard ? 1u << kGuardBit : 0u);
-        words[65 * p.waves + (tid >> 6)] = (uint32_t)wmin;
+        words[65 * p.waves + (tid >> 6)] =
+            (uint32_t)wmin |
+            (split ? 0u : (1u << kHalfBit) | ((uint32_t)ev_lo << kHalfLo) | ((uint32_t)ev_hi << kHalfHi));
       }
     }
   }
