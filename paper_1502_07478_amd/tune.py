@@ -86,16 +86,34 @@ def time_plans(g: jpet.Geometry, events: torch.Tensor, codes, rho: torch.Tensor 
     return [float(x) for x in ms]
 
 
+def with_families(g: jpet.Geometry, ranked, n: int, candidates: int, loglik: bool = False) -> list:
+    """The first `candidates` codes of a ranked list, plus the best-ranked code of every plan family
+    (register cache, row segments, wavefronts per workgroup) that has none among them: the cost
+    model's weights for a family (split rows above all) are priors, so each family gets timed."""
+    codes = list(ranked[:candidates])
+    def family(c):
+        li = jpet.launch_info(jpet.with_plan(g, c), n)
+        return li["row_cache"], li["row_segments"], li["waves"]
+    seen = {family(c) for c in codes}
+    for c in ranked[candidates:]:
+        f = family(c)
+        if f not in seen:
+            seen.add(f)
+            codes.append(c)
+    return codes
+
+
 def tune(g: jpet.Geometry, events: torch.Tensor, rho: torch.Tensor | None = None, candidates: int = 12,
          reps: int = 3, batched: bool = False) -> dict:
-    """Times the cost model's first `candidates` plans (for a batch: those the batched
-    pass can run) and returns {"code", "ms", "model_code", "model_ms", "timed", "seconds"}."""
+    """Times the cost model's first `candidates` plans and the best of every other plan family (for a
+    batch: among the plans the batched pass can run) and returns {"code", "ms", "model_code",
+    "model_ms", "timed", "seconds"}."""
     t0 = time.perf_counter()
     n = events.shape[0]
     ranked = [c for c, _ in jpet.plan_candidates(g, n)]
     if batched:
         ranked = [c for c in ranked if batchable(g, c, n)]
-    codes = ranked[:candidates]
+    codes = with_families(g, ranked, n, candidates)
     ms = time_plans(g, events, codes, rho, reps)
     timed = [(c, t) for c, t in zip(codes, ms) if t > 0]
     best = min(timed, key=lambda x: x[1]) if timed else (codes[0], -1.0)
@@ -128,9 +146,11 @@ def time_loglik_plans(g: jpet.Geometry, events: torch.Tensor, codes, rho: torch.
 def tune_loglik(g: jpet.Geometry, events: torch.Tensor, rho: torch.Tensor, s: torch.Tensor | None = None,
                 candidates: int = 8, reps: int = 3) -> dict:
     """The log-likelihood pass's counterpart of tune(): times the cost model's first `candidates` plans
-    of that pass (64-bit accumulators; whole or split rows) on these events and this image."""
+    of that pass (64-bit accumulators; whole or split rows), and the best of every other family, on
+    these events and this image."""
     t0 = time.perf_counter()
-    codes = [c for c, _ in jpet.plan_candidates(g, events.shape[0], loglik=True)][:candidates]
+    n = events.shape[0]
+    codes = with_families(g, [c for c, _ in jpet.plan_candidates(g, n, loglik=True)], n, candidates)
     ms = time_loglik_plans(g, events, codes, rho, s, reps)
     best = min(zip(codes, ms), key=lambda x: x[1])
     return {"code": int(best[0]), "ms": best[1], "model_code": int(codes[0]), "model_ms": ms[0],

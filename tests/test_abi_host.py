@@ -226,3 +226,28 @@ def test_binding_requires_built_library(monkeypatch, tmp_path):
     monkeypatch.setattr(jpet, "_L", None)
     with pytest.raises(RuntimeError, match="not built"):
         jpet.lib()
+
+
+def test_tuner_times_every_plan_family(lib):
+    """The tuner's candidate list: the cost model's leading plans, then the best-ranked plan of each
+    family (register cache, row segments, wavefronts) that has none among them, each once."""
+    from paper_1502_07478_amd import tune
+    from jpet_synth import get_workload
+    w = get_workload("large1024")
+    g = jpet.geometry(**w.geometry())
+    n = 8_000_000
+    ranked = [c for c, _ in jpet.plan_candidates(g, n)]
+
+    def family(c):
+        li = jpet.launch_info(jpet.with_plan(g, c), n)
+        return li["row_cache"], li["row_segments"], li["waves"]
+
+    codes = tune.with_families(g, ranked, n, 4)
+    assert codes[:4] == ranked[:4]
+    assert len(set(codes)) == len(codes)
+    fams = [family(c) for c in codes]
+    assert set(fams) == {family(c) for c in ranked}
+    # each added code is its family's best-ranked one
+    for c, f in zip(codes[4:], fams[4:]):
+        assert f not in fams[:4]
+        assert ranked.index(c) == min(i for i, r in enumerate(ranked) if family(r) == f)
