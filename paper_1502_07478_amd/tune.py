@@ -203,7 +203,7 @@ def _main():
     ap = argparse.ArgumentParser(description="Tune the event pass's plans of named workloads on this GPU and write "
                                              "them to a plan table (JSON).")
     ap.add_argument("--out", default=SHIPPED)
-    ap.add_argument("--workloads", default="prod400,grad200,grad200:loglik,large1024,batch64")
+    ap.add_argument("--workloads", default="prod400,grad200,grad200:loglik,large1024,batch64,paper130,edge400")
     ap.add_argument("--candidates", type=int, default=16)
     ap.add_argument("--reps", type=int, default=10)
     args = ap.parse_args()
