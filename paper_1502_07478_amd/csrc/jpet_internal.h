@@ -93,8 +93,8 @@ constexpr uint32_t kWordCol = 0, kWordRow = 8, kWordLen = 17, kWordEv = 24;
 //   its longest row (pixels; bit kGuardBit set when a row of the wavefront may reach kappa <= 0 and
 //   needs the per-pixel test);
 //   its shortest non-empty row (bits 0-7) and, with bit kHalfBit set, the one event of each
-//   half-wavefront's rows: lanes 0-31 in bits 8-12, lanes 32-63 in bits 16-20 (event 0 for a half
-//   with no rows).
+//   half-wavefront's rows: lanes 0-31 in bits 8-12, lanes 32-63 in bits 16-20 (a half with no rows
+//   names the other half's event).
 constexpr int kBlockTailWords = 2;
 constexpr uint32_t kGuardBit = 31;
 constexpr uint32_t kHalfBit = 31, kHalfLo = 8, kHalfHi = 16;

@@ -26,3 +26,25 @@ def test_traffic_figure_matches_the_counter_summary():
         assert f"sha256 prefix `{src}`" in text
         assert re.search(rf"\(plan {plan} from the plan table", text)
         assert f"({nbytes} bytes:" in text
+
+
+def test_source_hash_ignores_comments(tmp_path):
+    """The traffic figure follows the kernel code: a comment or blank line does not change the hash,
+    a code change does."""
+    import shutil
+    import bench
+    src = os.path.join(ROOT, "paper_1502_07478_amd", "csrc")
+    dst = tmp_path / "paper_1502_07478_amd" / "csrc"
+    shutil.copytree(src, dst)
+    root0 = bench.ROOT
+    try:
+        bench.ROOT = str(tmp_path)
+        h0 = bench.kernel_source_hash()
+        f = dst / "jpet_pass.hip"
+        text = f.read_text()
+        f.write_text("// a comment\n\n" + text.replace("namespace jpet {", "namespace jpet {  /* note */", 1))
+        assert bench.kernel_source_hash() == h0
+        f.write_text(text + "\nstatic int unused_probe = 0;\n")
+        assert bench.kernel_source_hash() != h0
+    finally:
+        bench.ROOT = root0
