@@ -655,7 +655,7 @@ constexpr int loglik_waves_per_simd() {
   return MAXLEN <= 16 ? 6 : 4;
 }
 
-template <int MAXLEN, int WAVES, bool VALUE>
+template <int MAXLEN, int WAVES, bool VALUE, int PITCH>
 __global__ void __launch_bounds__(WAVES * 64, loglik_waves_per_simd<MAXLEN>())
     k_loglik_tiled(Geo g, Plan p, const unsigned char* __restrict__ blocks, const BinItem* __restrict__ items,
                    const float* __restrict__ rho, double* __restrict__ B, float* __restrict__ D_out,
@@ -664,7 +664,7 @@ __global__ void __launch_bounds__(WAVES * 64, loglik_waves_per_simd<MAXLEN>())
   __shared__ PassShared ps;
   __shared__ GradShared gsh;
   if ((unsigned long long)blockIdx.x >= cnt[C_ITEMS]) return;  // uniform over the workgroup
-  event_pass_item<MAXLEN, WAVES, true, false, 0, VALUE>(g, p, blocks, items[blockIdx.x], rho,
+  event_pass_item<MAXLEN, WAVES, true, false, PITCH, VALUE>(g, p, blocks, items[blockIdx.x], rho,
                                                 reinterpret_cast<unsigned long long*>(B), cnt, smem, ps, &gsh, D_out,
                                                 red, evs);
 }
@@ -808,7 +808,8 @@ __global__ void k_update(int64_t npix, const float* __restrict__ s, float* __res
 template <int MAXLEN, int WAVES, bool ACC32>
 hipError_t launch_tiled(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, float* D_out,
                         hipStream_t st) {
-  auto kern = p.pitch == 128   ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 128>
+  auto kern = p.pitch == 64    ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 64>
+              : p.pitch == 128 ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 128>
               : p.pitch == 256 ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 256>
                                : k_event_pass_tiled<MAXLEN, WAVES, ACC32, 0>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
@@ -849,15 +850,25 @@ __global__ void k_update_batched(const BatchInst* __restrict__ table) {
   }
 }
 
-template <int MAXLEN, int WAVES>
-hipError_t launch_loglik_t(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, float* D_out,
+template <int MAXLEN, int WAVES, int PITCH>
+hipError_t launch_loglik_p(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, float* D_out,
                            bool value_only, hipStream_t st) {
-  auto kern = value_only ? k_loglik_tiled<MAXLEN, WAVES, true> : k_loglik_tiled<MAXLEN, WAVES, false>;
+  auto kern = value_only ? k_loglik_tiled<MAXLEN, WAVES, true, PITCH> : k_loglik_tiled<MAXLEN, WAVES, false, PITCH>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)p.max_items), dim3(64 * p.waves), p.lds_bytes, st, g, p, ws.batches,
                      ws.items, rho, ws.B, D_out, ws.red, ws.cnt, ws.evs);
   return hipGetLastError();
+}
+
+// regions whose row pitch is 64, 128 or 256 take kernels compiled for it (immediate LDS offsets)
+template <int MAXLEN, int WAVES>
+hipError_t launch_loglik_t(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, float* D_out,
+                           bool value_only, hipStream_t st) {
+  return p.pitch == 64    ? launch_loglik_p<MAXLEN, WAVES, 64>(g, p, ws, rho, D_out, value_only, st)
+         : p.pitch == 128 ? launch_loglik_p<MAXLEN, WAVES, 128>(g, p, ws, rho, D_out, value_only, st)
+         : p.pitch == 256 ? launch_loglik_p<MAXLEN, WAVES, 256>(g, p, ws, rho, D_out, value_only, st)
+                          : launch_loglik_p<MAXLEN, WAVES, 0>(g, p, ws, rho, D_out, value_only, st);
 }
 
 }  // namespace
