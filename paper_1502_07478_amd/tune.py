@@ -231,7 +231,7 @@ def _main():
             s = jpet.sensitivity(g, device=ev.device)
             rho = (s > 0).to(torch.float32)
             jpet.mlem_iterate(g, ev, rho, 5, s=s)
-            entry = tune_loglik(g, ev, rho, s, candidates=min(args.candidates, 8), reps=args.reps)
+            entry = tune_loglik(g, ev, rho, s, candidates=args.candidates, reps=args.reps)
         else:
             entry = tune(g, ev, candidates=args.candidates, reps=args.reps, batched=kind == "batched")
         entry["workload"] = w.name
