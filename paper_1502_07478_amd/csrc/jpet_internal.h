@@ -270,11 +270,13 @@ hipError_t launch_write_insts(const InstWrite& w, BatchInst* table, hipStream_t 
 hipError_t launch_batched_reset(const BatchInst* table, int count, hipStream_t st);
 // the batched pass over one class of a batch (table: the class's entries): 32-bit accumulators,
 // register cache maxlen (16, 32, 48 or 64), waves (8 or 16) wavefronts per workgroup, region row pitch
-// (64, 128, 256, or 0 for any other), one workgroup per item of the class (items in total)
+// (64, 128, 192, 256, or 0 for any other), one workgroup per item of the class (items in total)
 hipError_t launch_event_pass_batched(const BatchInst* table, int count, int maxlen, int waves, int pitch,
                                      size_t lds_bytes, int64_t items, hipStream_t st);
-// the pitch a batched class is compiled for: 64, 128 or 256, else 0 (a runtime value)
-inline int batched_pitch_class(int pitch) { return pitch == 64 || pitch == 128 || pitch == 256 ? pitch : 0; }
+// the pitch a batched class is compiled for: 64, 128, 192 or 256, else 0 (a runtime value)
+inline int batched_pitch_class(int pitch) {
+  return pitch == 64 || pitch == 128 || pitch == 192 || pitch == 256 ? pitch : 0;
+}
 // raises a batched pass's dynamic LDS limit (call before launching or capturing it)
 hipError_t set_batched_lds(int maxlen, int waves, int pitch, size_t lds_bytes);
 hipError_t launch_update_batched(const BatchInst* table, int count, int64_t max_npix, hipStream_t st);

@@ -810,6 +810,7 @@ hipError_t launch_tiled(const Geo& g, const Plan& p, const Workspace& ws, const 
                         hipStream_t st) {
   auto kern = p.pitch == 64    ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 64>
               : p.pitch == 128 ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 128>
+              : p.pitch == 192 ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 192>
               : p.pitch == 256 ? k_event_pass_tiled<MAXLEN, WAVES, ACC32, 256>
                                : k_event_pass_tiled<MAXLEN, WAVES, ACC32, 0>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
@@ -861,12 +862,13 @@ hipError_t launch_loglik_p(const Geo& g, const Plan& p, const Workspace& ws, con
   return hipGetLastError();
 }
 
-// regions whose row pitch is 64, 128 or 256 take kernels compiled for it (immediate LDS offsets)
+// regions whose row pitch is 64, 128, 192 or 256 take kernels compiled for it (immediate LDS offsets)
 template <int MAXLEN, int WAVES>
 hipError_t launch_loglik_t(const Geo& g, const Plan& p, const Workspace& ws, const float* rho, float* D_out,
                            bool value_only, hipStream_t st) {
   return p.pitch == 64    ? launch_loglik_p<MAXLEN, WAVES, 64>(g, p, ws, rho, D_out, value_only, st)
          : p.pitch == 128 ? launch_loglik_p<MAXLEN, WAVES, 128>(g, p, ws, rho, D_out, value_only, st)
+         : p.pitch == 192 ? launch_loglik_p<MAXLEN, WAVES, 192>(g, p, ws, rho, D_out, value_only, st)
          : p.pitch == 256 ? launch_loglik_p<MAXLEN, WAVES, 256>(g, p, ws, rho, D_out, value_only, st)
                           : launch_loglik_p<MAXLEN, WAVES, 0>(g, p, ws, rho, D_out, value_only, st);
 }
@@ -914,6 +916,7 @@ const void* batched_kernel_p(int pitch) {
   switch (pitch) {
     case 64: return (const void*)k_event_pass_batched<MAXLEN, WAVES, 64>;
     case 128: return (const void*)k_event_pass_batched<MAXLEN, WAVES, 128>;
+    case 192: return (const void*)k_event_pass_batched<MAXLEN, WAVES, 192>;
     case 256: return (const void*)k_event_pass_batched<MAXLEN, WAVES, 256>;
     default: return (const void*)k_event_pass_batched<MAXLEN, WAVES, 0>;
   }
@@ -939,6 +942,7 @@ hipError_t launch_batched_p(const BatchInst* table, int count, int pitch, unsign
   switch (pitch) {
     case 64: return launch_batched_t<MAXLEN, WAVES, 64>(table, count, items, lds_bytes, st);
     case 128: return launch_batched_t<MAXLEN, WAVES, 128>(table, count, items, lds_bytes, st);
+    case 192: return launch_batched_t<MAXLEN, WAVES, 192>(table, count, items, lds_bytes, st);
     case 256: return launch_batched_t<MAXLEN, WAVES, 256>(table, count, items, lds_bytes, st);
     default: return launch_batched_t<MAXLEN, WAVES, 0>(table, count, items, lds_bytes, st);
   }
