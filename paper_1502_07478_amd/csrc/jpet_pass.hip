@@ -252,8 +252,11 @@ __device__ __forceinline__ void copy_consts(const unsigned char* __restrict__ sr
 // The region is stored column-major with a row pitch that is a multiple of the LDS bank count.
 // Each thread owns the pixel row its thread word names (built at prepare time so that a
 // wavefront holds rows of nearly equal length, consecutive within each half-wavefront), so the
-// pixel at column offset j of every lane's row falls into a different bank whatever the slant of
-// the ellipse.
+// pixel at column offset j of the rows of one half-wavefront falls into 32 different banks
+// whatever the slant of the ellipse.  The two halves of a ring wavefront hold rings of two events
+// of the same bin, whose rows overlap, and may meet in a bank; tip wavefronts mix rows of several
+// events.  Measured at 400x400: conflict cycles are 20% of the LDS-active cycles, and moving every
+// lane's word to its own bank (a timing-only copy) saved 1% of the pass.
 // One workgroup item.  GRAD = false: the MLEM event pass (acc: 2^-32 fixed-point image; the LDS
 // accumulators are 64-bit in 2^-32 units, or with ACC32 32-bit in 2^-acc_shift units, acc_shift = 23
 // for items of up to 511 events).

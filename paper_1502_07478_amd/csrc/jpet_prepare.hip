@@ -251,7 +251,8 @@ __device__ EvRow event_row_constants(const Geo& g, const EventRec& e, int rbase,
 // 16 below ring k-1) and a remainder at its two tips.  Half-wavefront slots take the rings ordered
 // by ring index, then by group, so a wavefront pairs two rings at the same distance from their
 // ellipses' centres; the tips of all groups fill the remaining threads.  Within a half-wavefront
-// the rows are consecutive, which keeps the pass's LDS accesses free of bank conflicts.
+// the rows are consecutive, so its LDS accesses fall into distinct banks (the two halves of a
+// wavefront can still meet in a bank).
 constexpr int kBuildBatch = 32;
 constexpr int kBuildGroups = 2 * kBuildBatch;
 constexpr int kBuildSlots = 64;
