@@ -239,8 +239,11 @@ int jpet_loglik_grad(const jpet_geometry* g, const double* sigma_mask, const flo
  * the Sec. 4 listing with Eq. 3).  Instances that fit the binned pass are grouped into classes by
  * kernel configuration (register cache, wavefronts per workgroup, workgroups per CU, region row
  * pitch); per iteration each class is one launch with one workgroup per workgroup item of its
- * instances, the items in order of decreasing size.  Instances that fit only the generic pass get their own
- * launches.  A plan named in an instance's jpet_geometry.plan must be one the batched pass can run:
+ * instances, the items in order of decreasing size.  The classes are shared by the caller's stream
+ * and a second stream of the library's (one per device, default priority, created by the first
+ * batched call and kept until the process ends), forked from and joined back into the caller's
+ * stream within each iteration, so one class's last workgroups overlap another's work.  Instances
+ * that fit only the generic pass get their own launches.  A plan named in an instance's jpet_geometry.plan must be one the batched pass can run:
  * 32-bit accumulators (else JPET_EDOMAIN); plan 0 takes the cost model's cheapest such plan.  Each instance's result is that of jpet_mlem_iterate on it
  * alone with the same plan, to FP32 rounding of the denominators.
  * Host struct; pointers as for jpet_mlem_iterate. */

@@ -395,12 +395,15 @@ struct BatchClass {
   int pitch = 0;             // region row pitch the class is compiled for (0: a runtime value)
   size_t lds = 0;
   int64_t items = 0;         // workgroup items of the class's instances (set once they are prepared)
+  double cost = 0.0;         // estimated pairs of those items (set with items)
+  int stream = 0;            // 0: the caller's stream, 1: the batch's second stream
 };
 
 struct BatchLayout {
   std::vector<Plan> plan;       // per instance
   std::vector<size_t> off;      // per instance: byte offset of its workspace
   std::vector<int> order;       // table position -> instance
+  std::vector<double> work;     // per instance: estimated pairs of one full workgroup item
   std::vector<BatchClass> cls;  // the batched launches
   int64_t max_npix = 0;
   size_t total = 0;
@@ -413,7 +416,8 @@ BatchLayout batch_layout(const jpet_instance* inst, int count) {
   BatchLayout L;
   L.plan.resize(count);
   L.off.resize(count);
-  std::vector<double> work(count, 0.0);
+  std::vector<double>& work = L.work;
+  work.assign(count, 0.0);
   std::vector<int> key(count, 1 << 30);  // class key; generic instances last
   std::vector<PlanCand> cand;
   for (int k = 0; k < count; ++k) {
@@ -957,12 +961,25 @@ static int batched_items(int32_t count, BatchLayout* L, const std::vector<Worksp
   item_begin->assign((size_t)count, 0);
   for (BatchClass& C : L->cls) {
     C.items = 0;
+    C.cost = 0.0;
     for (int t = C.first; t < C.first + C.count; ++t) {
       const int k = L->order[t];
       (*item_begin)[k] = C.items;
       C.items += (int64_t)items[k];
+      C.cost += (double)items[k] * L->work[k];
     }
     if (C.items > 0x7fffffffll) return JPET_EINVAL;  // the launch grid is 32-bit
+  }
+  // two streams share the classes, heaviest first to the lighter one, so that one class's tail
+  // overlaps another class's work
+  std::vector<int> by_cost(L->cls.size());
+  for (size_t c = 0; c < by_cost.size(); ++c) by_cost[c] = (int)c;
+  std::stable_sort(by_cost.begin(), by_cost.end(), [&](int a, int b) { return L->cls[a].cost > L->cls[b].cost; });
+  double load[2] = {0.0, 0.0};
+  for (int c : by_cost) {
+    const int s = load[1] < load[0] ? 1 : 0;
+    L->cls[c].stream = s;
+    load[s] += L->cls[c].cost;
   }
   return JPET_OK;
 }
@@ -1006,21 +1023,62 @@ static int batched_setup(const jpet_instance* inst, int32_t count, const BatchLa
   return JPET_OK;
 }
 
+// The batched pass's second stream on the current device (default priority) with its fork and join
+// events: created on first use, outside any capture (batched_begin), kept until the process ends.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+static std::mutex g_side_mu;
+static std::vector<SideStream> g_side;  // per device
+
+static int side_stream(SideStream* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  if ((int)g_side.size() <= dev) g_side.resize((size_t)dev + 1);
+  SideStream& S = g_side[(size_t)dev];
+  if (!S.s) {
+    if ((e = hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e);
+    if ((e = hipEventCreateWithFlags(&S.fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
+    if ((e = hipEventCreateWithFlags(&S.join, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
+  }
+  *out = S;
+  return JPET_OK;
+}
+
 // n_iter iterations of a set-up batch: per iteration the counters' reset, one batched pass per
-// class over its instances' items, the generic instances' passes and the pixel update of all.
+// class over its instances' items (the classes shared by the caller's stream and the second
+// stream, joined before the update), the generic instances' passes and the pixel update of all.
 static int batched_iterations(const jpet_instance* inst, int32_t count, int32_t n_iter, const BatchLayout& L,
                               const std::vector<Workspace>& w, const std::vector<Geo>& geo, void* ws, bool timing,
                               hipStream_t st) {
   BatchInst* table = reinterpret_cast<BatchInst*>(ws);
   hipError_t e;
+  SideStream side;
+  const bool two = L.cls.size() > 1;
+  if (two) {
+    const int rc = side_stream(&side);
+    if (rc) return rc;
+  }
   for (int it = 0; it < n_iter; ++it) {
     if ((e = launch_batched_reset(table, count, st)) != hipSuccess) return hip_fail(e);
     if (!L.cls.empty()) {
       auto pass = [&] {
         hipError_t r = hipSuccess;
+        if (two) {
+          r = hipEventRecord(side.fork, st);
+          if (r == hipSuccess) r = hipStreamWaitEvent(side.s, side.fork, 0);
+        }
         for (size_t c = 0; c < L.cls.size() && r == hipSuccess; ++c) {
           const BatchClass& C = L.cls[c];
-          r = launch_event_pass_batched(table + C.first, C.count, C.maxlen, C.waves, C.pitch, C.lds, C.items, st);
+          r = launch_event_pass_batched(table + C.first, C.count, C.maxlen, C.waves, C.pitch, C.lds, C.items,
+                                        two && C.stream == 1 ? side.s : st);
+        }
+        if (two && r == hipSuccess) {
+          r = hipEventRecord(side.join, side.s);
+          if (r == hipSuccess) r = hipStreamWaitEvent(st, side.join, 0);
         }
         return r;
       };
@@ -1066,6 +1124,10 @@ static int batched_begin(const jpet_instance* inst, int32_t count, void* ws, siz
   }
   std::vector<int64_t> item_begin;
   if ((rc = batched_items(count, L, *w, st, &item_begin))) return rc;
+  if (L->cls.size() > 1) {
+    SideStream side;
+    if ((rc = side_stream(&side))) return rc;
+  }
   return batched_setup(inst, count, *L, *w, *geo, item_begin, ws, st);
 }
 
