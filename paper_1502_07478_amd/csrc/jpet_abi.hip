@@ -396,8 +396,11 @@ struct BatchClass {
   size_t lds = 0;
   int64_t items = 0;         // workgroup items of the class's instances (set once they are prepared)
   double cost = 0.0;         // estimated pairs of those items (set with items)
-  int stream = 0;            // 0: the caller's stream, 1: the batch's second stream
+  int stream = 0;            // 0: the caller's stream, k > 0: the batch's k-th side stream
 };
+
+// Streams that share a batch's class launches: the caller's and kBatchStreams - 1 of the library's.
+constexpr int kBatchStreams = 2;
 
 struct BatchLayout {
   std::vector<Plan> plan;       // per instance
@@ -405,6 +408,8 @@ struct BatchLayout {
   std::vector<int> order;       // table position -> instance
   std::vector<double> work;     // per instance: estimated pairs of one full workgroup item
   std::vector<BatchClass> cls;  // the batched launches
+  std::vector<int> launch;      // class indices in launch order: heaviest first
+  int streams = 1;              // streams the classes are spread over
   int64_t max_npix = 0;
   size_t total = 0;
   bool invalid = false;         // a named plan does not fit its geometry or the batched pass
@@ -970,14 +975,19 @@ static int batched_items(int32_t count, BatchLayout* L, const std::vector<Worksp
     }
     if (C.items > 0x7fffffffll) return JPET_EINVAL;  // the launch grid is 32-bit
   }
-  // two streams share the classes, heaviest first to the lighter one, so that one class's tail
-  // overlaps another class's work
-  std::vector<int> by_cost(L->cls.size());
+  // the streams share the classes, heaviest first to the least loaded one, so that one class's
+  // tail overlaps another class's work; each stream launches its classes heaviest first, so that
+  // the streams end on their lightest classes
+  std::vector<int>& by_cost = L->launch;
+  by_cost.resize(L->cls.size());
   for (size_t c = 0; c < by_cost.size(); ++c) by_cost[c] = (int)c;
   std::stable_sort(by_cost.begin(), by_cost.end(), [&](int a, int b) { return L->cls[a].cost > L->cls[b].cost; });
-  double load[2] = {0.0, 0.0};
+  L->streams = std::max(1, std::min(kBatchStreams, (int)L->cls.size()));
+  double load[kBatchStreams] = {};
   for (int c : by_cost) {
-    const int s = load[1] < load[0] ? 1 : 0;
+    int s = 0;
+    for (int q = 1; q < L->streams; ++q)
+      if (load[q] < load[s]) s = q;
     L->cls[c].stream = s;
     load[s] += L->cls[c].cost;
   }
@@ -1023,11 +1033,12 @@ static int batched_setup(const jpet_instance* inst, int32_t count, const BatchLa
   return JPET_OK;
 }
 
-// The batched pass's second stream on the current device (default priority) with its fork and join
-// events: created on first use, outside any capture (batched_begin), kept until the process ends.
+// The batched pass's side streams on the current device (default priority) with the fork event
+// and one join event each: created on first use, outside any capture (batched_begin), kept until
+// the process ends.
 struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t s[kBatchStreams - 1] = {};
+  hipEvent_t fork = nullptr, join[kBatchStreams - 1] = {};
 };
 static std::mutex g_side_mu;
 static std::vector<SideStream> g_side;  // per device
@@ -1039,26 +1050,28 @@ static int side_stream(SideStream* out) {
   std::lock_guard<std::mutex> lk(g_side_mu);
   if ((int)g_side.size() <= dev) g_side.resize((size_t)dev + 1);
   SideStream& S = g_side[(size_t)dev];
-  if (!S.s) {
-    if ((e = hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e);
+  if (!S.fork) {
+    for (int q = 0; q < kBatchStreams - 1; ++q) {
+      if ((e = hipStreamCreateWithFlags(&S.s[q], hipStreamNonBlocking)) != hipSuccess) return hip_fail(e);
+      if ((e = hipEventCreateWithFlags(&S.join[q], hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
+    }
     if ((e = hipEventCreateWithFlags(&S.fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
-    if ((e = hipEventCreateWithFlags(&S.join, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
   }
   *out = S;
   return JPET_OK;
 }
 
 // n_iter iterations of a set-up batch: per iteration the counters' reset, one batched pass per
-// class over its instances' items (the classes shared by the caller's stream and the second
-// stream, joined before the update), the generic instances' passes and the pixel update of all.
+// class over its instances' items (the classes shared by the caller's stream and the side
+// streams, joined before the update), the generic instances' passes and the pixel update of all.
 static int batched_iterations(const jpet_instance* inst, int32_t count, int32_t n_iter, const BatchLayout& L,
                               const std::vector<Workspace>& w, const std::vector<Geo>& geo, void* ws, bool timing,
                               hipStream_t st) {
   BatchInst* table = reinterpret_cast<BatchInst*>(ws);
   hipError_t e;
   SideStream side;
-  const bool two = L.cls.size() > 1;
-  if (two) {
+  const int ns = L.streams;
+  if (ns > 1) {
     const int rc = side_stream(&side);
     if (rc) return rc;
   }
@@ -1067,18 +1080,16 @@ static int batched_iterations(const jpet_instance* inst, int32_t count, int32_t 
     if (!L.cls.empty()) {
       auto pass = [&] {
         hipError_t r = hipSuccess;
-        if (two) {
-          r = hipEventRecord(side.fork, st);
-          if (r == hipSuccess) r = hipStreamWaitEvent(side.s, side.fork, 0);
-        }
-        for (size_t c = 0; c < L.cls.size() && r == hipSuccess; ++c) {
-          const BatchClass& C = L.cls[c];
+        if (ns > 1) r = hipEventRecord(side.fork, st);
+        for (int q = 1; q < ns && r == hipSuccess; ++q) r = hipStreamWaitEvent(side.s[q - 1], side.fork, 0);
+        for (size_t i = 0; i < L.launch.size() && r == hipSuccess; ++i) {
+          const BatchClass& C = L.cls[(size_t)L.launch[i]];
           r = launch_event_pass_batched(table + C.first, C.count, C.maxlen, C.waves, C.pitch, C.lds, C.items,
-                                        two && C.stream == 1 ? side.s : st);
+                                        C.stream > 0 ? side.s[C.stream - 1] : st);
         }
-        if (two && r == hipSuccess) {
-          r = hipEventRecord(side.join, side.s);
-          if (r == hipSuccess) r = hipStreamWaitEvent(st, side.join, 0);
+        for (int q = 1; q < ns && r == hipSuccess; ++q) {
+          r = hipEventRecord(side.join[q - 1], side.s[q - 1]);
+          if (r == hipSuccess) r = hipStreamWaitEvent(st, side.join[q - 1], 0);
         }
         return r;
       };
@@ -1124,7 +1135,7 @@ static int batched_begin(const jpet_instance* inst, int32_t count, void* ws, siz
   }
   std::vector<int64_t> item_begin;
   if ((rc = batched_items(count, L, *w, st, &item_begin))) return rc;
-  if (L->cls.size() > 1) {
+  if (L->streams > 1) {
     SideStream side;
     if ((rc = side_stream(&side))) return rc;
   }
